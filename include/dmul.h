@@ -1,0 +1,154 @@
+/*
+ * dmul -- exact product of two decimal integers on an AMD Instinct MI355X
+ * (gfx950), by the two-prime number-theoretic-transform method of
+ * "Speeding up decimal multiplication" (V. Krapivensky, 2020).
+ *
+ * Number format (Section 3.2, with base B = 10^19 for input and output):
+ *   an integer X = sum_i a[i] * 10^(19 i) is an array of little-endian
+ *   uint64_t limbs, every limb in [0, 10^19).  Leading zero limbs are
+ *   allowed; an empty array (length 0) is the integer 0.
+ *
+ * Result: Z = X * Y as exactly na + nb limbs in [0, 10^19); the top limb(s)
+ *   may be zero, nothing is normalised away (Section 3.2: the product of an
+ *   n-digit and an m-digit number has n + m digits).
+ *
+ * Method (done entirely by HIP kernels on the device): the limbs are re-cut
+ * into base-10^k digit groups with the largest k in [13, 18] such that
+ * (10^k - 1)^2 * min(n_k, m_k) < p1 * p2 (eq. ci_bound as the range
+ * condition of eq. product_inequality; n_k = ceil(19 na / k) counts every
+ * limb as 19 digits), the groups are convolved cyclically at the length
+ * N = 2^ceil(log2(n_k + m_k)) (Section 3.2) modulo the two primes
+ *   p1 = 9223371564408373249 = 1073741769 * 2^33 + 1,
+ *   p2 = 9223371938070528001 = 2147483625 * 2^32 + 1
+ * (the two largest primes c*3*2^n + 1 < 2^63 with c odd and n >= 32,
+ * Section 4.5) by two-pass NTTs with Montgomery arithmetic (Sections 4.4.3,
+ * 5, 6, 7), and every coefficient is recovered by the two-prime CRT and
+ * carried into base 10^19 (Section 8.2).  The result is bit-exact.
+ *
+ * Pointers: unless a function says "host", every limb pointer is a DEVICE
+ * pointer (HBM, e.g. a torch tensor's data_ptr()) on the context's device.
+ * The caller owns a, b and out; the library never frees them and does not
+ * keep them past the call (dmul) or past dmul_sync (dmul_ex, dmul_batch).
+ * The library owns its scratch, tables and status words, released by
+ * dmul_ctx_destroy.
+ *
+ * Aliasing: a == b with na == nb (squaring, the self-convolution case the
+ * paper supports in Section 6) is allowed and takes a cheaper path.  out must
+ * not overlap a or b (DMUL_EINVAL).
+ *
+ * Threads: a context is used by one host thread at a time.  dmul() uses a
+ * default context per device, guarded by a lock.
+ */
+#ifndef DMUL_H
+#define DMUL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes (0 = success, negative = error). */
+#define DMUL_OK 0
+#define DMUL_EINVAL (-1)   /* NULL pointer with nonzero length, overlap, bad flags */
+#define DMUL_EDIGIT (-2)   /* some limb >= 10^19 (found on the device; out unspecified) */
+#define DMUL_ERANGE (-3)   /* transform longer than the device path supports, or a forced k
+                              that breaks the convolution bound */
+#define DMUL_ENOMEM (-4)   /* workspace above the context budget, or allocation failed */
+#define DMUL_EDEVICE (-5)  /* a HIP runtime error */
+
+/* Flags.  DMUL_FLAG_FORCE_K(k) forces the digit-group size k (13..18); the
+ * call fails with DMUL_ERANGE if that k breaks the bound.  The product does
+ * not depend on k. */
+#define DMUL_FLAG_FORCE_K(k) ((unsigned)(k) & 0x1fu)
+#define DMUL_FLAG_K_MASK 0x1fu
+
+typedef struct dmul_ctx dmul_ctx;
+
+/* Plan of one product, as chosen by the library (Section 3.2 padding rule,
+ * Section 7.9 split N = R * C with R = 2^floor(log2 N / 2)). */
+typedef struct dmul_plan_info {
+  int32_t k;            /* decimal digits per group */
+  int32_t log2_n;       /* N = 2^log2_n */
+  int32_t log2_rows;    /* R */
+  int32_t log2_cols;    /* C */
+  uint64_t groups_a;    /* n_k */
+  uint64_t groups_b;    /* m_k */
+  uint64_t workspace_bytes;
+} dmul_plan_info;
+
+/* dmul: Z = X * Y, blocking.  a, b, out: device pointers on the current HIP
+ * device; na, nb: limb counts.  Runs on that device's default context and
+ * stream (the null stream unless dmul_ctx_set_stream was called on the
+ * default context) and returns once out is complete.  Returns DMUL_OK or a
+ * negative DMUL_E* code.  na == 0 or nb == 0 writes na + nb zero limbs. */
+int dmul(const uint64_t* a, size_t na, const uint64_t* b, size_t nb, uint64_t* out);
+
+/* Context on `device` with a workspace budget in bytes (0 = no limit).
+ * Returns DMUL_OK and *ctx, or DMUL_EDEVICE / DMUL_ENOMEM. */
+int dmul_ctx_create(dmul_ctx** ctx, int device, size_t hbm_budget_bytes);
+/* Waits for the context's work, then frees everything it owns. */
+int dmul_ctx_destroy(dmul_ctx* ctx);
+/* The HIP stream (hipStream_t passed as void*) the context enqueues on;
+ * NULL selects the null stream.  The stream stays owned by the caller. */
+int dmul_ctx_set_stream(dmul_ctx* ctx, void* hip_stream);
+
+/* Asynchronous product: enqueues the whole product on the context's stream
+ * and returns.  Argument errors are returned at once; a bad limb is
+ * reported by the next dmul_sync.  `flags`: 0 or DMUL_FLAG_FORCE_K(k). */
+int dmul_ex(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
+            uint64_t* out, unsigned flags);
+/* Waits for everything enqueued on the context; returns DMUL_OK, or the
+ * first error seen on the device since the last dmul_sync (DMUL_EDIGIT /
+ * DMUL_EDEVICE).  */
+int dmul_sync(dmul_ctx* ctx);
+
+/* Batched products: count independent products, operand i given by the
+ * device pointers a[i], b[i] and limb counts na[i], nb[i], result in out[i]
+ * (na[i] + nb[i] limbs).  a, na, b, nb, out and status are HOST arrays of
+ * length count.  All products are enqueued on the context's stream, grouped
+ * into one launch per phase and transform length (so a batch needs a fixed
+ * number of launches, not one set per product); dmul_sync completes it.
+ * status[i] (host memory, written by dmul_sync) receives each product's own
+ * code.  Returns DMUL_OK or the first argument error (then nothing is
+ * enqueued).  `flags` as for dmul_ex, applied to every product. */
+int dmul_batch(dmul_ctx* ctx, size_t count, const uint64_t* const* a, const size_t* na,
+               const uint64_t* const* b, const size_t* nb, uint64_t* const* out,
+               int32_t* status, unsigned flags);
+
+/* Planning, no device work: the plan for na x nb limbs (DMUL_OK, or
+ * DMUL_ERANGE / DMUL_EINVAL). */
+int dmul_plan(size_t na, size_t nb, unsigned flags, dmul_plan_info* info);
+/* Device workspace one product of na x nb limbs needs, in bytes (used for
+ * admission by footprint); 0 if the product is out of range. */
+size_t dmul_workspace_bytes(size_t na, size_t nb);
+
+/* Human-readable text for a status code (static storage). */
+const char* dmul_strerror(int code);
+
+/* Host-pointer convenience: copies a and b (HOST arrays) to the device,
+ * multiplies on `device`, copies the na + nb limbs back into out (HOST).
+ * For tests and tools; not for throughput. */
+int dmul_host(int device, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
+              uint64_t* out, unsigned flags);
+
+/* The two primes (p[0] < p[1]) and the smallest generators g[] of their
+ * multiplicative groups used for the roots of unity xi_N = g^((p-1)/N). */
+void dmul_primes(uint64_t p[2], uint64_t g[2]);
+
+/* Debug view of the convolution step alone: writes res[0..N) and
+ * res[N..2N) = the cyclic convolution of the digit groups of a and b modulo
+ * p1 and modulo p2 (device pointer `res` of 2N words, N from dmul_plan),
+ * blocking.  For tests of the transform separately from answer recovery. */
+int dmul_debug_residues(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b,
+                        size_t nb, uint64_t* res, unsigned flags);
+
+/* Library version string. */
+const char* dmul_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMUL_H */

@@ -1,0 +1,296 @@
+"""Python binding of libdmul (the gfx950 decimal multiplier).
+
+Argument marshalling only: every step of a product runs in the library's
+HIP kernels, reached through the C ABI declared in ``include/dmul.h``.
+PyTorch provides device memory (uint64 tensors) and streams.  There is no
+CPU fallback: if the library is not built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Sequence
+
+import numpy as np
+
+try:  # torch first, so libdmul binds to the HIP runtime torch already loaded
+    import torch
+except Exception:  # pragma: no cover - torch is part of the image
+    torch = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmul.so")
+
+DMUL_OK = 0
+DMUL_EINVAL = -1
+DMUL_EDIGIT = -2
+DMUL_ERANGE = -3
+DMUL_ENOMEM = -4
+DMUL_EDEVICE = -5
+
+# Every function the header declares (checked by the test suite).
+EXPORTS = ("dmul", "dmul_ctx_create", "dmul_ctx_destroy", "dmul_ctx_set_stream", "dmul_ex",
+           "dmul_sync", "dmul_batch", "dmul_plan", "dmul_workspace_bytes", "dmul_strerror",
+           "dmul_host", "dmul_primes", "dmul_debug_residues", "dmul_version")
+
+
+class DmulError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        msg = f"{what}: " if what else ""
+        super().__init__(f"{msg}{strerror(code)} ({code})")
+        self.code = code
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("log2_n", ctypes.c_int32), ("log2_rows", ctypes.c_int32),
+                ("log2_cols", ctypes.c_int32), ("groups_a", ctypes.c_uint64),
+                ("groups_b", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64)]
+
+
+@dataclass
+class Plan:
+    k: int
+    log2_n: int
+    log2_rows: int
+    log2_cols: int
+    groups_a: int
+    groups_b: int
+    workspace_bytes: int
+
+    @property
+    def N(self) -> int:
+        return 1 << self.log2_n
+
+
+_lib = None
+
+
+def lib():
+    """Load libdmul.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "or python paper_2011_11524_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    vp = ctypes.c_void_p
+    sz = ctypes.c_size_t
+    L.dmul.argtypes = [vp, sz, vp, sz, vp]
+    L.dmul_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, sz]
+    L.dmul_ctx_destroy.argtypes = [vp]
+    L.dmul_ctx_set_stream.argtypes = [vp, vp]
+    L.dmul_ex.argtypes = [vp, vp, sz, vp, sz, vp, ctypes.c_uint]
+    L.dmul_sync.argtypes = [vp]
+    L.dmul_batch.argtypes = [vp, sz, ctypes.POINTER(vp), ctypes.POINTER(sz), ctypes.POINTER(vp),
+                             ctypes.POINTER(sz), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int32),
+                             ctypes.c_uint]
+    L.dmul_plan.argtypes = [sz, sz, ctypes.c_uint, ctypes.POINTER(_PlanInfo)]
+    L.dmul_workspace_bytes.argtypes = [sz, sz]
+    L.dmul_workspace_bytes.restype = sz
+    L.dmul_strerror.argtypes = [ctypes.c_int]
+    L.dmul_strerror.restype = ctypes.c_char_p
+    L.dmul_host.argtypes = [ctypes.c_int, u64p, sz, u64p, sz, u64p, ctypes.c_uint]
+    L.dmul_primes.argtypes = [u64p, u64p]
+    L.dmul_primes.restype = None
+    L.dmul_debug_residues.argtypes = [vp, vp, sz, vp, sz, vp, ctypes.c_uint]
+    L.dmul_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().dmul_strerror(int(code)).decode()
+    except RuntimeError:
+        return f"dmul status {code}"
+
+
+def flags_for(force_k: int = 0) -> int:
+    return int(force_k) & 0x1F
+
+
+def primes() -> tuple[list[int], list[int]]:
+    p = (ctypes.c_uint64 * 2)()
+    g = (ctypes.c_uint64 * 2)()
+    lib().dmul_primes(p, g)
+    return [int(p[0]), int(p[1])], [int(g[0]), int(g[1])]
+
+
+def plan(na: int, nb: int, force_k: int = 0) -> Plan:
+    info = _PlanInfo()
+    rc = lib().dmul_plan(int(na), int(nb), flags_for(force_k), ctypes.byref(info))
+    if rc:
+        raise DmulError(rc, "dmul_plan")
+    return Plan(info.k, info.log2_n, info.log2_rows, info.log2_cols, info.groups_a,
+                info.groups_b, info.workspace_bytes)
+
+
+def workspace_bytes(na: int, nb: int) -> int:
+    return int(lib().dmul_workspace_bytes(int(na), int(nb)))
+
+
+def _check_limbs(t, name: str):
+    if torch is None or not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.uint64 or t.dim() != 1 or not t.is_contiguous() or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a contiguous 1-D torch.uint64 CUDA tensor")
+
+
+class Context:
+    """A dmul context: device tables, workspace, a stream (default: torch's
+    current stream on the device at creation time)."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, stream=None):
+        self._lib = lib()
+        h = ctypes.c_void_p()
+        rc = self._lib.dmul_ctx_create(ctypes.byref(h), int(device), int(budget_bytes))
+        if rc:
+            raise DmulError(rc, "dmul_ctx_create")
+        self._h = h
+        self.device = int(device)
+        self.set_stream(stream if stream is not None else torch.cuda.current_stream(self.device))
+
+    def set_stream(self, stream) -> None:
+        ptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+        self.stream = stream
+        rc = self._lib.dmul_ctx_set_stream(self._h, ctypes.c_void_p(ptr))
+        if rc:
+            raise DmulError(rc, "dmul_ctx_set_stream")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.dmul_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- single products ----------------------------------------------------
+    def mul_async(self, a, b, out, force_k: int = 0) -> None:
+        _check_limbs(a, "a")
+        _check_limbs(b, "b")
+        _check_limbs(out, "out")
+        if out.numel() != a.numel() + b.numel():
+            raise ValueError("out must hold len(a) + len(b) limbs")
+        rc = self._lib.dmul_ex(self._h, ctypes.c_void_p(a.data_ptr()), a.numel(),
+                               ctypes.c_void_p(b.data_ptr()), b.numel(),
+                               ctypes.c_void_p(out.data_ptr()), flags_for(force_k))
+        if rc:
+            raise DmulError(rc, "dmul_ex")
+
+    def sync(self) -> None:
+        rc = self._lib.dmul_sync(self._h)
+        if rc:
+            raise DmulError(rc, "dmul_sync")
+
+    def mul(self, a, b, force_k: int = 0, out=None):
+        if out is None:
+            out = torch.empty(a.numel() + b.numel(), dtype=torch.uint64, device=a.device)
+        self.mul_async(a, b, out, force_k)
+        self.sync()
+        return out
+
+    # -- batches -------------------------------------------------------------
+    def batch_async(self, pairs: Sequence, outs: Sequence, force_k: int = 0):
+        """Enqueue len(pairs) products (a_i, b_i) -> outs[i]; returns the host
+        status array that sync() fills in."""
+        n = len(pairs)
+        A = (ctypes.c_void_p * n)()
+        B = (ctypes.c_void_p * n)()
+        O = (ctypes.c_void_p * n)()
+        NA = (ctypes.c_size_t * n)()
+        NB = (ctypes.c_size_t * n)()
+        st = (ctypes.c_int32 * n)()
+        for i, ((a, b), o) in enumerate(zip(pairs, outs)):
+            A[i] = a.data_ptr() if a.numel() else 0
+            B[i] = b.data_ptr() if b.numel() else 0
+            O[i] = o.data_ptr() if o.numel() else 0
+            NA[i] = a.numel()
+            NB[i] = b.numel()
+        rc = self._lib.dmul_batch(self._h, n, A, NA, B, NB, O, st, flags_for(force_k))
+        if rc:
+            raise DmulError(rc, "dmul_batch")
+        self._keep = (A, B, O, NA, NB)
+        return st
+
+    def batch(self, pairs: Sequence, force_k: int = 0):
+        outs = [torch.empty(a.numel() + b.numel(), dtype=torch.uint64, device=a.device)
+                for a, b in pairs]
+        st = self.batch_async(pairs, outs, force_k)
+        self.sync()
+        return outs, [int(s) for s in st]
+
+    # -- debug view of the convolution ---------------------------------------
+    def residues(self, a, b, force_k: int = 0):
+        """The cyclic convolution of the digit groups of a and b mod p1 and mod
+        p2 (two length-N uint64 tensors)."""
+        pl = plan(a.numel(), b.numel(), force_k)
+        res = torch.empty(2 * pl.N, dtype=torch.uint64, device=a.device)
+        rc = self._lib.dmul_debug_residues(self._h, ctypes.c_void_p(a.data_ptr()), a.numel(),
+                                           ctypes.c_void_p(b.data_ptr()), b.numel(),
+                                           ctypes.c_void_p(res.data_ptr()), flags_for(force_k))
+        if rc:
+            raise DmulError(rc, "dmul_debug_residues")
+        return res[: pl.N], res[pl.N:]
+
+
+def to_device(limbs, device: int = 0):
+    """numpy uint64 limbs -> CUDA uint64 tensor."""
+    arr = np.ascontiguousarray(np.asarray(limbs, dtype=np.uint64))
+    return torch.from_numpy(arr).to(f"cuda:{device}")
+
+
+def to_host(t) -> np.ndarray:
+    return t.cpu().numpy()
+
+
+def mul(a, b, force_k: int = 0):
+    """Z = X * Y with the device's default context (blocking).  a, b: CUDA
+    uint64 tensors; returns a new tensor of len(a) + len(b) limbs."""
+    _check_limbs(a, "a")
+    _check_limbs(b, "b")
+    out = torch.empty(a.numel() + b.numel(), dtype=torch.uint64, device=a.device)
+    if force_k:
+        ctx = _default_context(a.device.index or 0)
+        return ctx.mul(a, b, force_k, out)
+    with torch.cuda.device(a.device):
+        rc = lib().dmul(ctypes.c_void_p(a.data_ptr() if a.numel() else 0), a.numel(),
+                        ctypes.c_void_p(b.data_ptr() if b.numel() else 0), b.numel(),
+                        ctypes.c_void_p(out.data_ptr() if out.numel() else 0))
+    if rc:
+        raise DmulError(rc, "dmul")
+    return out
+
+
+def mul_host(a, b, force_k: int = 0, device: int = 0) -> np.ndarray:
+    """Host-array convenience (copies in and out); for tests and tools."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.uint64))
+    out = np.zeros(len(a) + len(b), dtype=np.uint64)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    rc = lib().dmul_host(int(device), a.ctypes.data_as(u64p), len(a), b.ctypes.data_as(u64p), len(b),
+                         out.ctypes.data_as(u64p), flags_for(force_k))
+    if rc:
+        raise DmulError(rc, "dmul_host")
+    return out
+
+
+_contexts: dict[int, Context] = {}
+
+
+def _default_context(device: int) -> Context:
+    if device not in _contexts:
+        _contexts[device] = Context(device)
+    return _contexts[device]

@@ -1,0 +1,529 @@
+// C ABI of the decimal multiplier: contexts, planning, the single-product
+// path (dmul, dmul_ex), batches (dmul_batch) and status handling.
+//
+// Host-side work here is only the plan (Section 3.2 padding rule, the base
+// choice of Section 4.3 as a bound check, the N = R*C split of Section 7.9),
+// the one-time constants of the field (Section 4.4.3 Montgomery form,
+// Section 6 scale R^2 N^-1, Section 8.2.2 r~) and root tables (Section 5.5).
+// Every step of a product runs in the kernels of ntt.hip and carry.hip.
+#include <dmul.h>
+
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "batch.hpp"
+#include "ctx.hpp"
+
+using namespace dmi;
+typedef unsigned __int128 u128;
+
+namespace {
+
+// The primes: FindPrimes(w = 64, n_min = 32, l = 2) of Section 4.5, i.e.
+// the two largest primes c*3*2^n + 1 < 2^63 with c odd and n >= 32.
+// n >= 32 makes p == 1 (mod 2^32), which the word-serial REDC relies on.
+constexpr uint64_t kP[2] = {9223371564408373249ULL, 9223371938070528001ULL};
+// Smallest generators of F_p^*, and the prime factors of p - 1 that prove it.
+constexpr uint64_t kG[2] = {13, 19};
+const std::vector<uint64_t> kPm1Factors[2] = {{2, 3, 119304641ULL}, {2, 3, 5, 7, 199, 4111}};
+
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t p) { return (uint64_t)((u128)a * b % p); }
+uint64_t powmod(uint64_t a, uint64_t e, uint64_t p) {
+  uint64_t r = 1;
+  a %= p;
+  while (e) {
+    if (e & 1) r = mulmod(r, a, p);
+    a = mulmod(a, a, p);
+    e >>= 1;
+  }
+  return r;
+}
+uint64_t inv_mod(uint64_t a, uint64_t p) { return powmod(a, p - 2, p); }
+// Montgomery form x*R mod p, R = 2^64 (Section 4.4.3).
+uint64_t to_mont(uint64_t x, uint64_t p) { return (uint64_t)(((u128)(x % p) << 64) % p); }
+
+bool check_field() {
+  for (int i = 0; i < 2; ++i) {
+    const uint64_t p = kP[i];
+    if ((p & 0xffffffffULL) != 1) return false;
+    if (p >= (1ULL << 63)) return false;
+    uint64_t m = p - 1;
+    for (uint64_t q : kPm1Factors[i]) {
+      if (powmod(kG[i], (p - 1) / q, p) == 1) return false;
+      while (m % q == 0) m /= q;
+    }
+    if (m != 1) return false;   // the factor list is complete
+  }
+  return kP[0] < kP[1];
+}
+
+// Granlund-Montgomery magic numbers for floor(x / 10^e), x < 2^64:
+// floor(x / 10^e) = floor((x >> e) / 5^e), and for inputs below 2^(64-e)
+// the multiplier m = floor(2^(64-e+l) / 5^e) + 1 with l = ceil(log2 5^e)
+// gives floor(x' / 5^e) = (x' * m) >> (64 - e + l).
+DivTable make_div_table() {
+  DivTable t{};
+  uint64_t p10 = 1, p5 = 1;
+  for (int e = 0; e < 20; ++e) {
+    t.pow10[e] = p10;
+    if (e == 0) {
+      t.mag[0] = 1;
+      t.sh[0] = 0;
+    } else {
+      int l = 0;
+      while (((u128)1 << l) < p5) ++l;
+      const int nbits = 64 - e;
+      const u128 m = (((u128)1 << (nbits + l)) / p5) + 1;
+      t.mag[e] = (uint64_t)m;
+      t.sh[e] = (uint32_t)(nbits + l - 64);
+    }
+    if (e < 19) p10 *= 10;
+    if (e < 19) p5 *= 5;
+    if (e == 19) break;
+  }
+  return t;
+}
+
+bool check_div_table(const DivTable& t) {
+  uint64_t s = 0x9e3779b97f4a7c15ULL;
+  for (int e = 1; e < 20; ++e) {
+    const uint64_t d = t.pow10[e];
+    for (int it = 0; it < 4000; ++it) {
+      s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+      uint64_t x;
+      switch (it & 3) {
+        case 0: x = s; break;
+        case 1: x = s % 10000000000000000000ULL; break;
+        case 2: x = d * (s % (~0ULL / d)) + (it & 4 ? d - 1 : 0); break;
+        default: x = ~0ULL - (s & 0xffff); break;
+      }
+      const uint64_t q = (uint64_t)(((u128)(x >> e) * t.mag[e]) >> 64) >> t.sh[e];
+      if (q != x / d) return false;
+    }
+  }
+  return true;
+}
+
+int from_hip(hipError_t e) { return e == hipSuccess ? DMUL_OK : (e == hipErrorOutOfMemory ? DMUL_ENOMEM : DMUL_EDEVICE); }
+
+}  // namespace
+
+
+namespace dmi {
+
+int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl) {
+  if (flags & ~DMUL_FLAG_K_MASK) return DMUL_EINVAL;
+  const int fk = (int)(flags & DMUL_FLAG_K_MASK);
+  if (fk && (fk < kMinK || fk > 18)) return DMUL_EINVAL;
+  if (na == 0 || nb == 0) return DMUL_EINVAL;
+  if (na > ((size_t)1 << 40) || nb > ((size_t)1 << 40)) return DMUL_ERANGE;
+  const u128 P = (u128)kP[0] * kP[1];
+  int k = 0;
+  uint64_t nk = 0, mk = 0;
+  for (int kk = 18; kk >= kMinK; --kk) {
+    if (fk && kk != fk) continue;
+    const uint64_t a = (19 * (uint64_t)na + kk - 1) / kk;
+    const uint64_t b = (19 * (uint64_t)nb + kk - 1) / kk;
+    const uint64_t mn = a < b ? a : b;
+    uint64_t B1 = 1;
+    for (int i = 0; i < kk; ++i) B1 *= 10;
+    B1 -= 1;
+    const u128 L = (u128)B1 * B1;
+    if (L <= (P - 1) / mn) { k = kk; nk = a; mk = b; break; }
+  }
+  if (!k) return DMUL_ERANGE;
+  int logN = 0;
+  while (((uint64_t)1 << logN) < nk + mk) ++logN;
+  if (logN < 2) logN = 2;
+  if (logN > kMaxLogN) return DMUL_ERANGE;
+  pl->na = na;
+  pl->nb = nb;
+  pl->n = nk;
+  pl->m = mk;
+  pl->k = k;
+  pl->logN = logN;
+  pl->N = (uint64_t)1 << logN;
+  pl->logR = logN / 2;
+  pl->logC = logN - pl->logR;
+  return DMUL_OK;
+}
+
+size_t workspace_words(const PlanDev& pl) { return 4 * (size_t)pl.N; }
+
+// Builds (once per length) the inter-pass factor tables of a transform of
+// length N = R*C and returns pointers to them.
+int get_twiddles(dmul_ctx* ctx, int logN, int logR, TwiddleSet* tw) {
+  const size_t L1 = ((size_t)1 << kMaxLogLen) - 1;
+  for (int i = 0; i < 2; ++i) {
+    tw->len_fwd[i] = ctx->d_roots + (size_t)(2 * i) * L1;
+    tw->len_inv[i] = ctx->d_roots + (size_t)(2 * i + 1) * L1;
+  }
+  const int logC = logN - logR;
+  const size_t R = (size_t)1 << logR, C = (size_t)1 << logC, N = R * C;
+  auto it = ctx->pass.find(logN);
+  if (it == ctx->pass.end()) {
+    std::vector<uint64_t> h(2 * (2 * R + 2 * C));
+    for (int i = 0; i < 2; ++i) {
+      const uint64_t p = kP[i];
+      const uint64_t xi = powmod(kG[i], (p - 1) / N, p);   // primitive N-th root
+      const uint64_t xinv = inv_mod(xi, p);
+      const uint64_t scale = mulmod(to_mont(1, p), inv_mod(N % p, p), p);   // R * N^-1
+      uint64_t* base = h.data() + (size_t)i * (2 * R + 2 * C);
+      uint64_t* hf = base;
+      uint64_t* lf = hf + R;
+      uint64_t* hi = lf + C;
+      uint64_t* li = hi + R;
+      const uint64_t xiC = powmod(xi, C, p), xinvC = powmod(xinv, C, p);
+      uint64_t a = 1, b = 1;
+      for (size_t e = 0; e < R; ++e) {
+        hf[e] = to_mont(a, p);
+        hi[e] = to_mont(b, p);
+        a = mulmod(a, xiC, p);
+        b = mulmod(b, xinvC, p);
+      }
+      a = 1;
+      b = 1;
+      for (size_t e = 0; e < C; ++e) {
+        lf[e] = to_mont(a, p);
+        li[e] = to_mont(mulmod(b, scale, p), p);
+        a = mulmod(a, xi, p);
+        b = mulmod(b, xinv, p);
+      }
+    }
+    PassTables pt;
+    hipError_t e = hipMalloc(&pt.dev, h.size() * sizeof(uint64_t));
+    if (e != hipSuccess) return from_hip(e);
+    e = hipMemcpy(pt.dev, h.data(), h.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(pt.dev);
+      return from_hip(e);
+    }
+    it = ctx->pass.emplace(logN, pt).first;
+  }
+  for (int i = 0; i < 2; ++i) {
+    const uint64_t* base = it->second.dev + (size_t)i * (2 * R + 2 * C);
+    tw->hi_fwd[i] = base;
+    tw->lo_fwd[i] = base + R;
+    tw->hi_inv[i] = base + R + C;
+    tw->lo_inv[i] = base + 2 * R + C;
+  }
+  return DMUL_OK;
+}
+
+// Workspace of at least `words` 64-bit words (waits for queued work before
+// replacing a smaller one).
+int ensure_workspace(dmul_ctx* ctx, size_t words) {
+  if (ctx->ws_words >= words) return DMUL_OK;
+  if (ctx->budget && words * sizeof(uint64_t) > ctx->budget) return DMUL_ENOMEM;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return from_hip(e);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  ctx->ws = nullptr;
+  ctx->ws_words = 0;
+  e = hipMalloc(&ctx->ws, words * sizeof(uint64_t));
+  if (e != hipSuccess) return from_hip(e);
+  ctx->ws_words = words;
+  return DMUL_OK;
+}
+
+int ensure_status(dmul_ctx* ctx, size_t n) {
+  if (ctx->status_cap >= n) return DMUL_OK;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return from_hip(e);
+  int* d = nullptr;
+  e = hipMalloc(&d, n * sizeof(int));
+  if (e != hipSuccess) return from_hip(e);
+  e = hipMemset(d, 0, n * sizeof(int));
+  if (e != hipSuccess) { (void)hipFree(d); return from_hip(e); }
+  if (ctx->d_status) {
+    int first = 0;
+    (void)hipMemcpy(&first, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost);
+    (void)hipMemcpy(d, &first, sizeof(int), hipMemcpyHostToDevice);
+    (void)hipFree(ctx->d_status);
+  }
+  ctx->d_status = d;
+  ctx->status_cap = n;
+  return DMUL_OK;
+}
+
+static bool overlaps(const uint64_t* x, size_t nx, const uint64_t* y, size_t ny) {
+  if (!nx || !ny) return false;
+  const uintptr_t a0 = (uintptr_t)x, a1 = a0 + nx * 8, b0 = (uintptr_t)y, b1 = b0 + ny * 8;
+  return a0 < b1 && b0 < a1;
+}
+
+int check_args(const uint64_t* a, size_t na, const uint64_t* b, size_t nb, const uint64_t* out) {
+  if ((na && !a) || (nb && !b) || (na + nb && !out)) return DMUL_EINVAL;
+  if (overlaps(out, na + nb, a, na) || overlaps(out, na + nb, b, nb)) return DMUL_EINVAL;
+  return DMUL_OK;
+}
+
+// Enqueues one whole product; `status` is the device word its bad-limb
+// check reports to.  With `residues` set, stops after the convolution and
+// copies both residue vectors there instead of recovering the answer.
+int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
+                    uint64_t* out, unsigned flags, int* status, uint64_t* residues) {
+  if (na == 0 || nb == 0) return from_hip(launch_zero(out, na + nb, ctx->stream));
+  PlanDev pl;
+  int rc = make_plan(na, nb, flags, &pl);
+  if (rc) return rc;
+  TwiddleSet tw;
+  rc = get_twiddles(ctx, pl.logN, pl.logR, &tw);
+  if (rc) return rc;
+  rc = ensure_workspace(ctx, workspace_words(pl));
+  if (rc) return rc;
+  const bool square = (a == b && na == nb);
+  hipError_t e = launch_forward(pl, ctx->cs, tw, ctx->d_div, a, b, square, ctx->ws, status, ctx->stream);
+  if (e == hipSuccess) e = launch_inverse(pl, ctx->cs, tw, ctx->ws, square, ctx->stream);
+  if (e != hipSuccess) return from_hip(e);
+  if (residues) {
+    e = hipMemcpyAsync(residues, ctx->ws, 2 * pl.N * sizeof(uint64_t), hipMemcpyDeviceToDevice, ctx->stream);
+    return from_hip(e);
+  }
+  e = launch_recover(pl, ctx->cs, ctx->d_div, ctx->ws, ctx->ws + pl.N, out, ctx->ws + 2 * pl.N, ctx->stream);
+  return from_hip(e);
+}
+
+}  // namespace dmi
+
+namespace {
+std::mutex g_default_mu;
+std::map<int, dmul_ctx*> g_default;
+
+dmul_ctx* default_ctx(int device, int* rc) {
+  std::lock_guard<std::mutex> lk(g_default_mu);
+  auto it = g_default.find(device);
+  if (it != g_default.end()) return it->second;
+  dmul_ctx* c = nullptr;
+  *rc = dmul_ctx_create(&c, device, 0);
+  if (*rc) return nullptr;
+  g_default[device] = c;
+  return c;
+}
+}  // namespace
+
+extern "C" {
+
+const char* dmul_version(void) { return "dmul-gfx950 1.0"; }
+
+const char* dmul_strerror(int code) {
+  switch (code) {
+    case DMUL_OK: return "ok";
+    case DMUL_EINVAL: return "invalid argument";
+    case DMUL_EDIGIT: return "limb >= 10^19 in an operand";
+    case DMUL_ERANGE: return "product outside the supported range";
+    case DMUL_ENOMEM: return "workspace above budget or device allocation failed";
+    case DMUL_EDEVICE: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+void dmul_primes(uint64_t p[2], uint64_t g[2]) {
+  p[0] = kP[0]; p[1] = kP[1];
+  g[0] = kG[0]; g[1] = kG[1];
+}
+
+int dmul_plan(size_t na, size_t nb, unsigned flags, dmul_plan_info* info) {
+  if (!info) return DMUL_EINVAL;
+  PlanDev pl;
+  const int rc = make_plan(na, nb, flags, &pl);
+  if (rc) return rc;
+  info->k = pl.k;
+  info->log2_n = pl.logN;
+  info->log2_rows = pl.logR;
+  info->log2_cols = pl.logC;
+  info->groups_a = pl.n;
+  info->groups_b = pl.m;
+  info->workspace_bytes = workspace_words(pl) * sizeof(uint64_t);
+  return DMUL_OK;
+}
+
+size_t dmul_workspace_bytes(size_t na, size_t nb) {
+  if (na == 0 || nb == 0) return 0;
+  PlanDev pl;
+  if (make_plan(na, nb, 0, &pl)) return 0;
+  return workspace_words(pl) * sizeof(uint64_t);
+}
+
+int dmul_ctx_create(dmul_ctx** out, int device, size_t budget) {
+  if (!out) return DMUL_EINVAL;
+  *out = nullptr;
+  if (!check_field()) return DMUL_EDEVICE;
+  const DivTable dt = make_div_table();
+  if (!check_div_table(dt)) return DMUL_EDEVICE;
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return from_hip(e);
+  dmul_ctx* c = new (std::nothrow) dmul_ctx;
+  if (!c) return DMUL_ENOMEM;
+  c->device = device;
+  c->budget = budget;
+  for (int i = 0; i < 2; ++i) {
+    c->cs.P[i].p = kP[i];
+    c->cs.P[i].p_hi = (uint32_t)(kP[i] >> 32);
+  }
+  c->cs.r_tilde = to_mont(inv_mod(kP[0] % kP[1], kP[1]), kP[1]);
+  // root tables: for every length 2^l, l = 1..kMaxLogLen, w^i (i < 2^(l-1))
+  const size_t L1 = ((size_t)1 << kMaxLogLen) - 1;
+  std::vector<uint64_t> roots(4 * L1);
+  for (int i = 0; i < 2; ++i) {
+    const uint64_t p = kP[i];
+    for (int l = 1; l <= kMaxLogLen; ++l) {
+      const uint64_t w = powmod(kG[i], (p - 1) >> l, p);
+      const uint64_t wi = inv_mod(w, p);
+      uint64_t* f = roots.data() + (size_t)(2 * i) * L1 + root_table_offset(l);
+      uint64_t* g = roots.data() + (size_t)(2 * i + 1) * L1 + root_table_offset(l);
+      uint64_t x = 1, y = 1;
+      for (size_t j = 0; j < ((size_t)1 << (l - 1)); ++j) {
+        f[j] = to_mont(x, p);
+        g[j] = to_mont(y, p);
+        x = mulmod(x, w, p);
+        y = mulmod(y, wi, p);
+      }
+    }
+  }
+  int rc = DMUL_OK;
+  e = hipMalloc(&c->d_roots, roots.size() * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMemcpy(c->d_roots, roots.data(), roots.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&c->d_div, sizeof(DivTable));
+  if (e == hipSuccess) e = hipMemcpy(c->d_div, &dt, sizeof(DivTable), hipMemcpyHostToDevice);
+  if (e != hipSuccess) rc = from_hip(e);
+  if (!rc) rc = ensure_status(c, 64);
+  if (rc) {
+    dmul_ctx_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return DMUL_OK;
+}
+
+int dmul_ctx_destroy(dmul_ctx* c) {
+  if (!c) return DMUL_EINVAL;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  delete c->batch;
+  for (auto& kv : c->pass) (void)hipFree(kv.second.dev);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->d_roots) (void)hipFree(c->d_roots);
+  if (c->d_div) (void)hipFree(c->d_div);
+  if (c->d_status) (void)hipFree(c->d_status);
+  delete c;
+  return DMUL_OK;
+}
+
+int dmul_ctx_set_stream(dmul_ctx* c, void* stream) {
+  if (!c) return DMUL_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->stream = (hipStream_t)stream;
+  return DMUL_OK;
+}
+
+int dmul_ex(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
+            uint64_t* out, unsigned flags) {
+  if (!c) return DMUL_EINVAL;
+  int rc = check_args(a, na, b, nb, out);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  rc = enqueue_product(c, a, na, b, nb, out, flags, c->d_status, nullptr);
+  if (rc == DMUL_EDEVICE && c->pending == DMUL_OK) c->pending = rc;
+  return rc;
+}
+
+int dmul_sync(dmul_ctx* c) {
+  if (!c) return DMUL_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  int rc = c->pending;
+  c->pending = DMUL_OK;
+  if (e != hipSuccess) rc = from_hip(e);
+  const size_t n = 1 + c->batch_count;
+  std::vector<int> st(n, 0);
+  e = hipMemcpy(st.data(), c->d_status, n * sizeof(int), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemset(c->d_status, 0, n * sizeof(int));
+  if (e != hipSuccess) return from_hip(e);
+  if (st[0] && rc == DMUL_OK) rc = DMUL_EDIGIT;
+  if (c->batch_status) {
+    for (size_t i = 0; i < c->batch_count; ++i)
+      if (st[1 + i] && c->batch_status[i] == DMUL_OK) c->batch_status[i] = DMUL_EDIGIT;
+  }
+  c->batch_status = nullptr;
+  c->batch_count = 0;
+  return rc;
+}
+
+int dmul(const uint64_t* a, size_t na, const uint64_t* b, size_t nb, uint64_t* out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DMUL_EDEVICE;
+  int rc = DMUL_OK;
+  dmul_ctx* c = default_ctx(dev, &rc);
+  if (!c) return rc;
+  rc = dmul_ex(c, a, na, b, nb, out, 0);
+  const int rs = dmul_sync(c);
+  return rc ? rc : rs;
+}
+
+int dmul_host(int device, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
+              uint64_t* out, unsigned flags) {
+  if ((na && !a) || (nb && !b) || (na + nb && !out)) return DMUL_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return DMUL_EDEVICE;
+  int rc = DMUL_OK;
+  dmul_ctx* c = default_ctx(device, &rc);
+  if (!c) return rc;
+  uint64_t *da = nullptr, *db = nullptr, *dz = nullptr;
+  hipError_t e = hipMalloc(&da, (na + 1) * 8);
+  if (e == hipSuccess) e = hipMalloc(&db, (nb + 1) * 8);
+  if (e == hipSuccess) e = hipMalloc(&dz, (na + nb + 1) * 8);
+  if (e == hipSuccess && na) e = hipMemcpy(da, a, na * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess && nb) e = hipMemcpy(db, b, nb * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    const bool same = (a == b && na == nb);
+    rc = dmul_ex(c, da, na, same ? da : db, nb, dz, flags);
+    const int rs = dmul_sync(c);
+    if (!rc) rc = rs;
+    if (!rc && na + nb) e = hipMemcpy(out, dz, (na + nb) * 8, hipMemcpyDeviceToHost);
+  }
+  if (e != hipSuccess && !rc) rc = from_hip(e);
+  if (da) (void)hipFree(da);
+  if (db) (void)hipFree(db);
+  if (dz) (void)hipFree(dz);
+  return rc;
+}
+
+int dmul_debug_residues(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
+                        uint64_t* res, unsigned flags) {
+  if (!c || !res || !na || !nb || !a || !b) return DMUL_EINVAL;
+  int rc;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    rc = enqueue_product(c, a, na, b, nb, nullptr, flags, c->d_status, res);
+  }
+  const int rs = dmul_sync(c);
+  return rc ? rc : rs;
+}
+
+int dmul_batch(dmul_ctx* c, size_t count, const uint64_t* const* a, const size_t* na,
+               const uint64_t* const* b, const size_t* nb, uint64_t* const* out,
+               int32_t* status, unsigned flags) {
+  if (!c || (count && (!a || !na || !b || !nb || !out || !status))) return DMUL_EINVAL;
+  if (flags & ~DMUL_FLAG_K_MASK) return DMUL_EINVAL;
+  for (size_t i = 0; i < count; ++i) {
+    const int rc = check_args(a[i], na[i], b[i], nb[i], out[i]);
+    if (rc) return rc;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = ensure_status(c, 1 + count);
+  if (rc) return rc;
+  for (size_t i = 0; i < count; ++i) status[i] = DMUL_OK;
+  if (!c->batch) {
+    c->batch = new (std::nothrow) BatchEngine();
+    if (!c->batch) return DMUL_ENOMEM;
+  }
+  rc = c->batch->run(c, count, a, na, b, nb, out, status, flags, c->d_status + 1);
+  c->batch_status = status;
+  c->batch_count = count;
+  if (rc == DMUL_EDEVICE && c->pending == DMUL_OK) c->pending = rc;
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,46 @@
+// Context object shared by the host-side pieces of the library.
+#pragma once
+#include <map>
+#include <mutex>
+
+#include <dmul.h>
+
+#include "internal.hpp"
+
+namespace dmi {
+class BatchEngine;
+struct PassTables {
+  uint64_t* dev = nullptr;   // per prime: hi_fwd[R] lo_fwd[C] hi_inv[R] lo_inv[C]
+};
+}  // namespace dmi
+
+using dmi::Consts;
+using dmi::DivTable;
+
+struct dmul_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  Consts cs{};
+  DivTable* d_div = nullptr;
+  uint64_t* d_roots = nullptr;          // [prime][dir] blocks of 2^kMaxLogLen - 1 words
+  std::map<int, dmi::PassTables> pass; // by log2 N
+  uint64_t* ws = nullptr;
+  size_t ws_words = 0;
+  int* d_status = nullptr;              // [0]: dmul_ex; [1 + i]: batch product i
+  size_t status_cap = 0;
+  int pending = DMUL_OK;
+  int32_t* batch_status = nullptr;      // host array to fill at dmul_sync
+  size_t batch_count = 0;
+  dmi::BatchEngine* batch = nullptr;
+  std::mutex mu;
+};
+
+namespace dmi {
+int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl);
+size_t workspace_words(const PlanDev& pl);
+int get_twiddles(dmul_ctx* ctx, int logN, int logR, TwiddleSet* tw);
+int ensure_workspace(dmul_ctx* ctx, size_t words);
+int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
+                    uint64_t* out, unsigned flags, int* status, uint64_t* residues);
+}  // namespace dmi

@@ -1,0 +1,72 @@
+// Shared declarations of the host library (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "field.hpp"
+
+namespace dmi {
+
+constexpr int kMaxLogN = 26;       // two LDS passes of at most 2^13 points each
+constexpr int kMaxLogLen = 13;     // longest sub-transform held in one workgroup's LDS
+constexpr int kMinK = 13;          // p1*p2 < 10^(3k): three base-10^k parts per coefficient
+constexpr uint64_t kLimbBase = 10000000000000000000ULL;  // 10^19
+
+// Magic multipliers for floor(x / 10^e), x < 2^64, e in [0, 19]:
+//   q = umulhi(x >> e, mag[e]) >> sh[e]    (e >= 1),  q = x  (e = 0)
+// i.e. division by 2^e by shifting, then by 5^e by a Granlund-Montgomery
+// multiply-high (division by invariant integers using multiplication).
+struct DivTable {
+  uint64_t mag[20];
+  uint32_t sh[20];
+  uint64_t pow10[20];
+};
+
+// Everything a kernel needs about one product, passed by value.
+struct PlanDev {
+  uint64_t na, nb;          // limbs of a and b (base 10^19)
+  uint64_t n, m;            // base-10^k groups of a and b
+  uint64_t N;               // transform length, 2^logN
+  int k;                    // digits per group
+  int logN, logR, logC;     // N = R*C, R = 2^logR rows, C = 2^logC columns
+};
+
+// Device-side constant data for both primes, built once per context.
+struct Consts {
+  Prime P[2];
+  uint64_t r_tilde;         // R * (p1^-1 mod p2) mod p2 (Montgomery form for the CRT)
+};
+
+// Per transform-length tables for the inter-pass factor xi_N^(+-e), e < N,
+// split e = e_hi*C + e_lo (Montgomery form; the inverse low table also
+// carries the scale R^2 N^-1 of the linearity trick).
+struct TwiddleSet {
+  const uint64_t* len_fwd[2];   // [prime] -> base of per-length root tables (forward roots)
+  const uint64_t* len_inv[2];   // [prime] -> same for inverse roots
+  const uint64_t* hi_fwd[2];
+  const uint64_t* lo_fwd[2];
+  const uint64_t* hi_inv[2];
+  const uint64_t* lo_inv[2];
+};
+
+// Offset of the table of w_L^i (i < L/2) for L = 2^l inside a per-prime
+// root-table block: tables for l = 1, 2, ... are stored back to back.
+__host__ __device__ constexpr size_t root_table_offset(int l) { return ((size_t)1 << (l - 1)) - 1; }
+
+// Launch wrappers (ntt.hip, carry.hip).  All enqueue on `stream` and return
+// hipSuccess or the launch error.
+hipError_t launch_forward(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
+                          const DivTable* dt, const uint64_t* a, const uint64_t* b, bool square,
+                          uint64_t* bufs /* 4*N words: X1 X2 Y1 Y2 */,
+                          int* status, hipStream_t stream);
+hipError_t launch_inverse(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
+                          uint64_t* bufs, bool square, hipStream_t stream);
+hipError_t launch_recover(const PlanDev& pl, const Consts& cs, const DivTable* dt,
+                          const uint64_t* res1,
+                          const uint64_t* res2, uint64_t* out, uint64_t* scratch,
+                          hipStream_t stream);
+size_t recover_scratch_words(const PlanDev& pl);
+hipError_t launch_zero(uint64_t* out, size_t n, hipStream_t stream);
+
+}  // namespace dmi

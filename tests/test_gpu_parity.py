@@ -1,0 +1,258 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every product is compared limb by limb -- integer work, so the bar is
+bit-exact -- against oracle O2 (the plain two-prime NTT), and on small
+sizes also against oracle O1 (schoolbook) and CPython's integer multiply.
+"""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import int_to_limbs, limbs_to_int
+
+pytestmark = pytest.mark.gpu
+
+P1 = 9223371564408373249
+P2 = 9223371938070528001
+
+
+@pytest.fixture(scope="module")
+def dm():
+    import torch
+    import paper_2011_11524_amd as dm
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dm.lib()
+    return dm
+
+
+@pytest.fixture(scope="module")
+def ctx(dm):
+    c = dm.Context(0)
+    yield c
+    c.close()
+
+
+def _note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _rand_limbs(rng, n):
+    return np.array([rng.randrange(10 ** 19) for _ in range(n)], dtype=np.uint64)
+
+
+def _gpu_mul(dm, ctx, a, b, force_k=0):
+    da = dm.to_device(a)
+    db = da if b is a else dm.to_device(b)
+    return dm.to_host(ctx.mul(da, db, force_k=force_k))
+
+
+SMALL = [(1, 1), (1, 2), (2, 1), (3, 5), (7, 7), (17, 31), (64, 3), (80, 80), (81, 81), (100, 1),
+         (1, 100), (255, 257), (1000, 1000), (1000, 37), (2049, 2047), (4000, 300), (5264, 5264)]
+
+
+@pytest.mark.parametrize("na,nb", SMALL)
+def test_random_products_match_oracle(dm, ctx, na, nb):
+    _note(f"random {na}x{nb}")
+    rng = random.Random(na * 7919 + nb)
+    a = _rand_limbs(rng, na)
+    b = _rand_limbs(rng, nb)
+    got = _gpu_mul(dm, ctx, a, b)
+    np.testing.assert_array_equal(got, oracle.mul_ntt(a, b))
+    if na * nb <= 10 ** 6:
+        np.testing.assert_array_equal(got, oracle.schoolbook(a, b))
+        assert limbs_to_int(got) == limbs_to_int(a) * limbs_to_int(b)
+
+
+@pytest.mark.parametrize("k", [13, 14, 15, 16, 17, 18])
+def test_forced_digit_group_sizes(dm, ctx, k):
+    rng = random.Random(k)
+    for na, nb in [(1, 1), (5, 9), (80, 33), (300, 1200)]:
+        if oracle.choose_k(na, nb, k) == 0:
+            continue
+        _note(f"force_k={k} {na}x{nb}")
+        a = _rand_limbs(rng, na)
+        b = _rand_limbs(rng, nb)
+        got = _gpu_mul(dm, ctx, a, b, force_k=k)
+        np.testing.assert_array_equal(got, oracle.mul_ntt(a, b, force_k=k))
+
+
+def _groups(x_limbs, k, count):
+    X = limbs_to_int(x_limbs)
+    B = 10 ** k
+    out = []
+    for _ in range(count):
+        X, r = divmod(X, B)
+        out.append(r)
+    return out
+
+
+@pytest.mark.parametrize("na,nb", [(1, 1), (3, 4), (40, 40), (100, 60), (400, 333)])
+def test_convolution_residues(dm, ctx, na, nb):
+    """The transform step alone: the device residues equal the cyclic
+    convolution of the digit groups mod each prime, computed with the
+    oracle's pinned transform (convolution theorem)."""
+    _note(f"residues {na}x{nb}")
+    rng = random.Random(na + 1000 * nb)
+    a = _rand_limbs(rng, na)
+    b = _rand_limbs(rng, nb)
+    pl = dm.plan(na, nb)
+    N = pl.N
+    x = _groups(a, pl.k, pl.groups_a) + [0] * (N - pl.groups_a)
+    y = _groups(b, pl.k, pl.groups_b) + [0] * (N - pl.groups_b)
+    r1, r2 = ctx.residues(dm.to_device(a), dm.to_device(b))
+    for p, got in ((P1, dm.to_host(r1)), (P2, dm.to_host(r2))):
+        g = oracle.generator(p)
+        xi = pow(g, (p - 1) // N, p)
+        fx = oracle.transform(x, p, xi)
+        fy = oracle.transform(y, p, xi)
+        prod = [int(u) * int(v) % p for u, v in zip(fx, fy)]
+        back = oracle.transform(prod, p, pow(xi, p - 2, p))
+        ninv = pow(N, p - 2, p)
+        want = np.array([int(v) * ninv % p for v in back], dtype=np.uint64)
+        np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("n", [1, 2, 50, 81, 777, 5264])
+def test_squaring_same_buffer(dm, ctx, n):
+    _note(f"square {n}")
+    rng = random.Random(n)
+    a = _rand_limbs(rng, n)
+    da = dm.to_device(a)
+    got = dm.to_host(ctx.mul(da, da))
+    np.testing.assert_array_equal(got, oracle.mul_ntt(a, a))
+
+
+@pytest.mark.parametrize("nl", [1, 2, 79, 80, 81, 7611, 7612, 716383])
+def test_all_nines_limbs_bound_edges(dm, ctx, nl):
+    """Operands of all 10^19-1 limbs, at the edges of the bound: the last
+    size with k = 18 (80 limbs), k = 17 (7611) and k = 16 (716,383 limbs,
+    13.6M digits, largest coefficient within 1e-6 of p1*p2)."""
+    _note(f"nines-limbs {nl}")
+    a = synth.repeated_limbs(10 ** 19 - 1, nl)
+    got = _gpu_mul(dm, ctx, a, a.copy())
+    np.testing.assert_array_equal(got, _nines_square_limbs(19 * nl, 2 * nl))
+    assert dm.plan(nl, nl).k == oracle.choose_k(nl, nl)
+
+
+def _nines_square_limbs(d, nlimbs):
+    dig = np.zeros(19 * nlimbs, dtype=np.uint8)
+    dig[0] = 1
+    dig[d] = 8
+    dig[d + 1:2 * d] = 9
+    return synth.pack_digits(dig)
+
+
+@pytest.mark.parametrize("d", [1530, 100_000])
+def test_all_nines_closed_form(dm, ctx, d):
+    _note(f"nines-closed {d}")
+    a = synth.all_nines(d)
+    got = _gpu_mul(dm, ctx, a, a.copy())
+    np.testing.assert_array_equal(got, _nines_square_limbs(d, 2 * len(a)))
+
+
+def test_c1_100k_digits_vs_schoolbook(dm, ctx):
+    _note("C1 100k x 100k")
+    a = synth.random_operand(100_000, 1001)
+    b = synth.random_operand(100_000, 1002)
+    got = _gpu_mul(dm, ctx, a, b)
+    np.testing.assert_array_equal(got, oracle.schoolbook(a, b))
+
+
+def test_c2_10m_digits_vs_oracle(dm, ctx):
+    _note("C2 10^7 x 10^7 random")
+    a = synth.random_operand(10 ** 7, 2001)
+    b = synth.random_operand(10 ** 7, 2002)
+    got = _gpu_mul(dm, ctx, a, b)
+    np.testing.assert_array_equal(got, oracle.mul_ntt(a, b))
+
+
+def test_c2_all_nines_closed_form(dm, ctx):
+    _note("C2 10^7 all nines")
+    d = 10 ** 7
+    a = synth.all_nines(d)
+    got = _gpu_mul(dm, ctx, a, a.copy())
+    np.testing.assert_array_equal(got, _nines_square_limbs(d, 2 * len(a)))
+
+
+@pytest.mark.parametrize("force_k", [0, 14])
+def test_c3_unbalanced_vs_oracle(dm, ctx, force_k):
+    _note(f"C3 4e7 x 2e7 force_k={force_k}")
+    a = synth.random_operand(4 * 10 ** 7, 3001)
+    b = synth.random_operand(2 * 10 ** 7, 3002)
+    got = _gpu_mul(dm, ctx, a, b, force_k=force_k)
+    np.testing.assert_array_equal(got, oracle.mul_ntt(a, b, force_k=force_k))
+
+
+def test_errors_and_empty(dm, ctx):
+    import torch
+    _note("errors")
+    a = dm.to_device(np.array([10 ** 19, 5], dtype=np.uint64))
+    b = dm.to_device(np.array([7], dtype=np.uint64))
+    with pytest.raises(dm.DmulError) as e:
+        ctx.mul(a, b)
+    assert e.value.code == dm.DMUL_EDIGIT
+    # the error is cleared: the next product succeeds
+    ok = ctx.mul(dm.to_device(np.array([3], np.uint64)), b)
+    assert dm.to_host(ok).tolist() == [21, 0]
+    # overlap of out with an input
+    buf = torch.zeros(8, dtype=torch.uint64, device="cuda")
+    with pytest.raises(dm.DmulError) as e:
+        ctx.mul_async(buf[:2], buf[2:4], buf[1:5])
+    assert e.value.code == dm.DMUL_EINVAL
+    # empty operand: zeros
+    z = dm.mul(torch.zeros(0, dtype=torch.uint64, device="cuda"), dm.to_device(np.array([9, 9], np.uint64)))
+    assert dm.to_host(z).tolist() == [0, 0]
+    # forced k beyond the bound
+    with pytest.raises(dm.DmulError) as e:
+        ctx.mul(dm.to_device(np.ones(81, np.uint64)), dm.to_device(np.ones(81, np.uint64)), force_k=18)
+    assert e.value.code == dm.DMUL_ERANGE
+
+
+def test_default_context_and_host_entry(dm):
+    _note("dmul() and dmul_host()")
+    rng = random.Random(99)
+    a = _rand_limbs(rng, 333)
+    b = _rand_limbs(rng, 444)
+    want = oracle.mul_ntt(a, b)
+    np.testing.assert_array_equal(dm.to_host(dm.mul(dm.to_device(a), dm.to_device(b))), want)
+    np.testing.assert_array_equal(dm.mul_host(a, b), want)
+    np.testing.assert_array_equal(dm.mul_host(a, b, force_k=15), want)
+
+
+def test_batch_matches_single_and_oracle(dm, ctx):
+    _note("batch mixed sizes")
+    rng = random.Random(4242)
+    sizes = [(1, 1), (5, 3), (80, 81), (700, 20), (20, 700), (1500, 1499), (3, 9000), (64, 64)]
+    host = [(_rand_limbs(rng, x), _rand_limbs(rng, y)) for x, y in sizes]
+    dev = [(dm.to_device(a), dm.to_device(b)) for a, b in host]
+    outs, st = ctx.batch(dev)
+    assert st == [0] * len(sizes)
+    for (a, b), o, (da, db) in zip(host, outs, dev):
+        want = oracle.mul_ntt(a, b)
+        np.testing.assert_array_equal(dm.to_host(o), want)
+        np.testing.assert_array_equal(dm.to_host(ctx.mul(da, db)), want)
+
+
+def test_batch_reports_per_product_status(dm, ctx):
+    _note("batch with one bad operand")
+    good = dm.to_device(np.array([1, 2, 3], np.uint64))
+    bad = dm.to_device(np.array([10 ** 19 + 1], np.uint64))
+    outs, st = ctx.batch([(good, good), (bad, good), (good, good)])
+    assert st[0] == 0 and st[1] == dm.DMUL_EDIGIT and st[2] == 0
+    np.testing.assert_array_equal(dm.to_host(outs[2]), oracle.mul_ntt([1, 2, 3], [1, 2, 3]))
+
+
+def test_repeatable(dm, ctx):
+    _note("determinism")
+    a = synth.random_operand(300_000, 7)
+    b = synth.random_operand(250_000, 8)
+    da, db = dm.to_device(a), dm.to_device(b)
+    first = dm.to_host(ctx.mul(da, db))
+    for _ in range(3):
+        np.testing.assert_array_equal(dm.to_host(ctx.mul(da, db)), first)
+    np.testing.assert_array_equal(first, oracle.mul_ntt(a, b))
