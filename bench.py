@@ -1,0 +1,292 @@
+#!/usr/bin/env python3
+"""Throughput of the gfx950 decimal multiplier.
+
+Default workload: one exact product of two random 10^7-digit integers
+(uniform digits, nonzero leading digit, seeds 2001/2002) held as base-10^19
+uint64 limbs in HBM.  A step is one whole product -- digit-group split, the
+forward NTTs of both operands modulo both primes, pointwise product, inverse
+NTTs, CRT, carry and regrouping -- enqueued through the C ABI (dmul_ex) on
+the context stream.  W untimed steps, then exactly K timed steps bracketed by
+torch.cuda.synchronize(); the product is checked bit for bit against the CPU
+oracle afterwards.
+
+Printed: one JSON line with the metric (decimal digits multiplied per
+second), the ALU roofline of the dominant kernel (per-kernel HIP-event
+durations on the launch stream), the algorithmic HBM rate of the NTT phases,
+the CPU oracle timed on this host, and (with --batched) the batched
+workload against one launch per product.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: one 32-bit VALU operation per lane
+# per clock (the fp32 vector rate of 157.3 TFLOP/s counts an FMA as two
+# flops and packed fp32 as two lanes).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+# Word-level operation counts of the field arithmetic (32-bit VALU ops),
+# from the formulas the kernels implement: a Montgomery product is six
+# 32x32->64 multiply-adds plus fourteen adds, negations, carries and the
+# final conditional subtraction; a modular add or subtract is a 64-bit
+# add/sub (2), compare (1), 64-bit correction (2), select (2).
+OPS_MODMUL = 20
+OPS_MODADD = 7
+OPS_LAZYSUB = 3
+OPS_DIF = OPS_MODADD + OPS_LAZYSUB + OPS_MODMUL     # x+y, (x-y+p)*w
+OPS_DIT = OPS_MODMUL + 2 * OPS_MODADD              # u = y*w, x+u, x-u
+OPS_BF1 = 2 * OPS_MODADD                           # factor 1: x+y, x-y
+OPS_SPLIT = 24      # two multiply-high divisions by powers of ten per group
+OPS_CRT = 120       # CRT modmul, 64x64 product, four 2-by-1 divisions
+OPS_CARRY = 12      # per position: carry map, scan step, digit
+
+
+def phase_work(N: int, logR: int, logC: int, arrays_fwd: int, NP: int, na: int, nb: int) -> dict:
+    """Algorithmic VALU operations and HBM bytes of each kernel phase."""
+    half = N // 2
+    fwd_stage = lambda logl: half * (OPS_BF1 + (logl - 1) * OPS_DIF)
+    inv_stage = lambda logl: half * (OPS_BF1 + (logl - 1) * OPS_DIT)
+    w = {}
+    w["fwd_cols"] = (arrays_fwd * (fwd_stage(logR) + N * (2 * OPS_MODMUL + OPS_SPLIT)),
+                     2 * 8 * (na + nb) + arrays_fwd * 8 * N)
+    w["fwd_rows"] = (arrays_fwd * fwd_stage(logC), arrays_fwd * 16 * N)
+    w["inv_rows"] = (2 * (N * OPS_MODMUL + inv_stage(logC)), 2 * 24 * N)
+    w["inv_cols"] = (2 * (2 * N * OPS_MODMUL + inv_stage(logR)), 2 * 16 * N)
+    w["rec_local"] = (NP * OPS_CRT, 24 * NP)
+    w["rec_blocks"] = (0, 0)
+    w["rec_apply"] = (NP * OPS_CARRY, 8 * NP + 8 * (na + nb))
+    return w
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("field.hpp", "ntt.hip", "carry.hip", "internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2011_11524_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str, per_launch_units: str):
+    """HBM traffic measured by rocprofv3 counters for `kernel`, if the stored
+    measurement was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if data.get("source_hash") != kernel_source_hash():
+        return None
+    ent = data.get("kernels", {}).get(kernel)
+    if not ent:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(a, b, budget_s: float, max_products: int):
+    import oracle
+    times = []
+    out = None
+    while len(times) < max_products and sum(times) < budget_s:
+        t0 = time.perf_counter()
+        out = oracle.mul_ntt(a, b)
+        times.append(time.perf_counter() - t0)
+    return out, times
+
+
+def run_batched(dm, ctx, torch, steps: int, warmup: int, count: int):
+    """The batched workload (4096 products, operand lengths log-uniform in
+    [10^3, 10^6] digits, aspect ratio in [1, 4]) as one dmul_batch against
+    one dmul_ex per product."""
+    import numpy as np
+    import synth
+    da, db = synth.batched_lengths(count)
+    rng = np.random.default_rng(4005)
+    pool = synth.OperandPool(10 ** 6, seed=4006, pool_limbs=4 * synth.limbs_for_digits(10 ** 6))
+    pairs, outs, digits = [], [], 0
+    for x, y in zip(da, db):
+        a = pool.take(int(x))
+        b = pool.take(int(y))
+        ta, tb = dm.to_device(a), dm.to_device(b)
+        pairs.append((ta, tb))
+        outs.append(torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda"))
+        digits += int(x) + int(y)
+    del rng
+
+    def one_by_one():
+        for (ta, tb), o in zip(pairs, outs):
+            ctx.mul_async(ta, tb, o)
+        ctx.sync()
+
+    def batched():
+        ctx.batch_async(pairs, outs)
+        ctx.sync()
+
+    res = {}
+    for name, fn in (("per_product", one_by_one), ("batched", batched)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res[name] = {"ms_per_batch": dt * 1e3, "digits_per_s": digits / dt}
+    res["products"] = count
+    res["digits"] = digits
+    res["speedup"] = res["per_product"]["ms_per_batch"] / res["batched"]["ms_per_batch"]
+    return res
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--digits", type=int, default=10 ** 7, help="digits of each operand")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time at most")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched", action="store_true", help="also run the batched workload")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent products shard across GPUs without communication; "
+              "see the design notes)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2011_11524_amd as dm
+    import synth
+
+    if not os.path.exists(dm.LIB_PATH):
+        from paper_2011_11524_amd import build as libbuild
+        libbuild.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    D = args.digits
+    a = synth.random_operand(D, 2001)
+    b = synth.random_operand(D, 2002)
+    pl = dm.plan(len(a), len(b))
+    ta, tb = dm.to_device(a), dm.to_device(b)
+    out = torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda")
+    ctx = dm.Context(0)
+
+    for _ in range(args.warmup):
+        ctx.mul_async(ta, tb, out)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.mul_async(ta, tb, out)
+    ctx.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    value = 2 * D / (elapsed / args.steps)
+    print(f"[bench] {args.steps} products of {D}x{D} digits: {ms_per_step:.3f} ms each", flush=True)
+
+    # per-kernel durations (events on the context stream), a separate pass
+    ctx.profile(True)
+    for _ in range(args.steps):
+        ctx.mul_async(ta, tb, out)
+    ctx.sync()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    NP = pl.groups_a + pl.groups_b
+    work = phase_work(pl.N, pl.log2_rows, pl.log2_cols, 4, NP, len(a), len(b))
+    phases = {}
+    for name, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        avg_s = ms / cnt / 1e3
+        ops, byt = work.get(name, (0, 0))
+        phases[name] = {"avg_us": avg_s * 1e6, "launches": cnt,
+                        "valu_tops": ops / avg_s / 1e12 if ops else 0.0,
+                        "hbm_gbs": byt / avg_s / 1e9 if byt else 0.0}
+    dominant = max(phases, key=lambda k: phases[k]["avg_us"])
+    d = phases[dominant]
+    ops_dom, bytes_dom = work[dominant]
+    roofline = {"bound": "alu", "kernel": dominant,
+                "achieved": round(d["valu_tops"], 3), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "TOP/s", "frac": round(d["valu_tops"] / VALU_PEAK_TOPS, 4),
+                "ops_per_launch": ops_dom, "bytes_per_launch": bytes_dom,
+                "traffic": traffic_for(dominant, "bytes")}
+    ntt = [k for k in ("fwd_cols", "fwd_rows", "inv_rows", "inv_cols") if k in phases]
+    ntt_s = sum(phases[k]["avg_us"] for k in ntt) / 1e6
+    ntt_bytes = sum(work[k][1] for k in ntt)
+    hbm = {"ntt_phases_gbs": round(ntt_bytes / ntt_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+           "frac": round(ntt_bytes / ntt_s / 1e9 / HBM_PEAK_GBS, 4), "ntt_bytes": ntt_bytes,
+           "ntt_us": round(ntt_s * 1e6, 2)}
+
+    got = out.cpu().numpy()
+    result = {
+        "metric": "decimal digits multiplied/sec (10^7x10^7)",
+        "value": value,
+        "unit": "digits/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"exact product of two random {D}-digit integers (base-10^19 limbs)",
+                   "digits_a": D, "digits_b": D, "limbs_a": len(a), "limbs_b": len(b),
+                   "k": pl.k, "N": pl.N, "layout": f"{1 << pl.log2_rows}x{1 << pl.log2_cols}",
+                   "seeds": [2001, 2002]},
+        "roofline": roofline,
+        "hbm": hbm,
+        "phases": {k: {kk: round(vv, 3) if isinstance(vv, float) else vv for kk, vv in v.items()}
+                   for k, v in phases.items()},
+    }
+
+    if args.batched:
+        result["batched"] = run_batched(dm, ctx, torch, max(1, args.steps // 10), 1, args.batch_count)
+
+    if not args.no_cpu_baseline:
+        want, times = cpu_baseline(a, b, args.cpu_budget, 3)
+        cores = 1
+        result["cpu_baseline"] = {"value": 2 * D / (sum(times) / len(times)), "unit": "digits/s",
+                                  "cores": cores, "kind": "oracle",
+                                  "sample": f"{len(times)} full {D}x{D}-digit products by the "
+                                            "oracle's plain two-prime NTT, single thread",
+                                  "host_cores_available": len(os.sched_getaffinity(0))}
+        result["parity"] = "bit-exact" if np.array_equal(got, want) else "MISMATCH"
+        if not np.array_equal(got, want):
+            print("[bench] MISMATCH against the oracle", file=sys.stderr, flush=True)
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    ctx.close()
+    print(json.dumps(result), flush=True)
+    return 0 if result.get("parity", "bit-exact") == "bit-exact" else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -144,6 +144,19 @@ void dmul_primes(uint64_t p[2], uint64_t g[2]);
 int dmul_debug_residues(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b,
                         size_t nb, uint64_t* res, unsigned flags);
 
+/* Measurement hooks.  dmul_ctx_profile(ctx, 1) makes every later product on
+ * the context record a HIP event on its stream after each kernel (and one
+ * before the first), and resets the totals; 0 turns it off.  The events
+ * cost a little time, so throughput is measured with profiling off.
+ * dmul_ctx_profile_read fills total_ms[i] (summed duration) and
+ * launches[i] (count) for kernel phase i < n, for products completed by a
+ * dmul_sync, and returns the number of phases; dmul_phase_name(i) names
+ * phase i ("fwd_cols", "fwd_rows", "inv_rows", "inv_cols", "rec_local",
+ * "rec_blocks", "rec_apply"). */
+int dmul_ctx_profile(dmul_ctx* ctx, int enable);
+int dmul_ctx_profile_read(dmul_ctx* ctx, double* total_ms, uint64_t* launches, int n);
+const char* dmul_phase_name(int phase);
+
 /* Library version string. */
 const char* dmul_version(void);
 

@@ -32,7 +32,8 @@ DMUL_EDEVICE = -5
 # Every function the header declares (checked by the test suite).
 EXPORTS = ("dmul", "dmul_ctx_create", "dmul_ctx_destroy", "dmul_ctx_set_stream", "dmul_ex",
            "dmul_sync", "dmul_batch", "dmul_plan", "dmul_workspace_bytes", "dmul_strerror",
-           "dmul_host", "dmul_primes", "dmul_debug_residues", "dmul_version")
+           "dmul_host", "dmul_primes", "dmul_debug_residues", "dmul_version", "dmul_ctx_profile",
+           "dmul_ctx_profile_read", "dmul_phase_name")
 
 
 class DmulError(RuntimeError):
@@ -97,6 +98,11 @@ def lib():
     L.dmul_primes.restype = None
     L.dmul_debug_residues.argtypes = [vp, vp, sz, vp, sz, vp, ctypes.c_uint]
     L.dmul_version.restype = ctypes.c_char_p
+    L.dmul_ctx_profile.argtypes = [vp, ctypes.c_int]
+    L.dmul_ctx_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
+    L.dmul_phase_name.argtypes = [ctypes.c_int]
+    L.dmul_phase_name.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -231,6 +237,21 @@ class Context:
         st = self.batch_async(pairs, outs, force_k)
         self.sync()
         return outs, [int(s) for s in st]
+
+    # -- per-kernel timing ----------------------------------------------------
+    def profile(self, enable: bool) -> None:
+        rc = self._lib.dmul_ctx_profile(self._h, 1 if enable else 0)
+        if rc:
+            raise DmulError(rc, "dmul_ctx_profile")
+
+    def profile_read(self) -> dict:
+        n = 16
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_uint64 * n)()
+        got = self._lib.dmul_ctx_profile_read(self._h, ms, cnt, n)
+        if got < 0:
+            raise DmulError(got, "dmul_ctx_profile_read")
+        return {self._lib.dmul_phase_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(got)}
 
     # -- debug view of the convolution ---------------------------------------
     def residues(self, a, b, force_k: int = 0):

@@ -275,14 +275,17 @@ int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t*
   rc = ensure_workspace(ctx, workspace_words(pl));
   if (rc) return rc;
   const bool square = (a == b && na == nb);
-  hipError_t e = launch_forward(pl, ctx->cs, tw, ctx->d_div, a, b, square, ctx->ws, status, ctx->stream);
-  if (e == hipSuccess) e = launch_inverse(pl, ctx->cs, tw, ctx->ws, square, ctx->stream);
+  Marks* marks = ctx->prof;
+  if (ctx->prof) ctx->prof->begin(ctx->stream);
+  hipError_t e = launch_forward(pl, ctx->cs, tw, ctx->d_div, a, b, square, ctx->ws, status, ctx->stream, marks);
+  if (e == hipSuccess) e = launch_inverse(pl, ctx->cs, tw, ctx->ws, square, ctx->stream, marks);
   if (e != hipSuccess) return from_hip(e);
   if (residues) {
     e = hipMemcpyAsync(residues, ctx->ws, 2 * pl.N * sizeof(uint64_t), hipMemcpyDeviceToDevice, ctx->stream);
     return from_hip(e);
   }
-  e = launch_recover(pl, ctx->cs, ctx->d_div, ctx->ws, ctx->ws + pl.N, out, ctx->ws + 2 * pl.N, ctx->stream);
+  e = launch_recover(pl, ctx->cs, ctx->d_div, ctx->ws, ctx->ws + pl.N, out, ctx->ws + 2 * pl.N, ctx->stream,
+                     marks);
   return from_hip(e);
 }
 
@@ -403,6 +406,7 @@ int dmul_ctx_destroy(dmul_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   delete c->batch;
+  delete c->prof;
   for (auto& kv : c->pass) (void)hipFree(kv.second.dev);
   if (c->ws) (void)hipFree(c->ws);
   if (c->d_roots) (void)hipFree(c->d_roots);
@@ -434,6 +438,7 @@ int dmul_sync(dmul_ctx* c) {
   if (!c) return DMUL_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
   hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && c->prof) c->prof->collect();
   int rc = c->pending;
   c->pending = DMUL_OK;
   if (e != hipSuccess) rc = from_hip(e);
@@ -500,6 +505,35 @@ int dmul_debug_residues(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_
   }
   const int rs = dmul_sync(c);
   return rc ? rc : rs;
+}
+
+int dmul_ctx_profile(dmul_ctx* c, int enable) {
+  if (!c) return DMUL_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  (void)hipStreamSynchronize(c->stream);
+  delete c->prof;
+  c->prof = nullptr;
+  if (enable) {
+    c->prof = new (std::nothrow) Profiler();
+    if (!c->prof) return DMUL_ENOMEM;
+  }
+  return DMUL_OK;
+}
+
+int dmul_ctx_profile_read(dmul_ctx* c, double* total_ms, uint64_t* launches, int n) {
+  if (!c || n < 0 || (n && (!total_ms || !launches))) return DMUL_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (int i = 0; i < n && i < kNumPhases; ++i) {
+    total_ms[i] = c->prof ? c->prof->total_ms[i] : 0.0;
+    launches[i] = c->prof ? c->prof->count[i] : 0;
+  }
+  return kNumPhases;
+}
+
+const char* dmul_phase_name(int phase) {
+  static const char* names[kNumPhases] = {"fwd_cols", "fwd_rows", "inv_rows", "inv_cols",
+                                          "rec_local", "rec_blocks", "rec_apply"};
+  return (phase >= 0 && phase < kNumPhases) ? names[phase] : "unknown";
 }
 
 int dmul_batch(dmul_ctx* c, size_t count, const uint64_t* const* a, const size_t* na,

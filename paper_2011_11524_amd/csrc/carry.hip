@@ -285,7 +285,7 @@ size_t recover_scratch_words(const PlanDev& pl) {
 
 hipError_t launch_recover(const PlanDev& pl, const Consts& cs, const DivTable* dt,
                           const uint64_t* res1, const uint64_t* res2, uint64_t* out,
-                          uint64_t* scratch, hipStream_t st) {
+                          uint64_t* scratch, hipStream_t st, Marks* marks) {
   RecConsts rc;
   rc.P2 = cs.P[1];
   rc.p1 = cs.P[0].p;
@@ -303,8 +303,11 @@ hipError_t launch_recover(const PlanDev& pl, const Consts& cs, const DivTable* d
   uint32_t* maps = (uint32_t*)(scratch + rc.NP);
   uint32_t* cins = maps + nblk;
   hipLaunchKernelGGL(k_rec_local, dim3((unsigned)nblk), dim3(kRecThreads), 0, st, rc, res1, res2, s, maps);
+  if (marks) marks->mark(kRecLocal, st);
   hipLaunchKernelGGL(k_rec_blocks, dim3(1), dim3(kRecThreads), 0, st, maps, cins, (uint32_t)nblk);
+  if (marks) marks->mark(kRecBlocks, st);
   hipLaunchKernelGGL(k_rec_apply, dim3((unsigned)nblk), dim3(kRecThreads), 0, st, rc, dt, s, maps, cins, out);
+  if (marks) marks->mark(kRecApply, st);
   return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 #include <map>
 #include <mutex>
+#include <vector>
 
 #include <dmul.h>
 
@@ -11,6 +12,55 @@ namespace dmi {
 class BatchEngine;
 struct PassTables {
   uint64_t* dev = nullptr;   // per prime: hi_fwd[R] lo_fwd[C] hi_inv[R] lo_inv[C]
+};
+
+// Per-kernel event timing (dmul_ctx_profile): an event before the first
+// kernel of a product and one after every kernel; durations are collected
+// at dmul_sync.
+struct Profiler : Marks {
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  size_t last = 0;
+  struct Span { int phase; size_t a, b; };
+  std::vector<Span> spans;
+  double total_ms[kNumPhases] = {};
+  uint64_t count[kNumPhases] = {};
+
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void begin(hipStream_t st) {
+    last = used;
+    hipEvent_t e = next();
+    if (e) (void)hipEventRecord(e, st);
+  }
+  void mark(int phase, hipStream_t st) override {
+    const size_t i = used;
+    hipEvent_t e = next();
+    if (!e) return;
+    (void)hipEventRecord(e, st);
+    spans.push_back({phase, last, i});
+    last = i;
+  }
+  void collect() {
+    for (const Span& s : spans) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pool[s.a], pool[s.b]) == hipSuccess) {
+        total_ms[s.phase] += ms;
+        count[s.phase] += 1;
+      }
+    }
+    spans.clear();
+    used = 0;
+  }
+  ~Profiler() override {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
 };
 }  // namespace dmi
 
@@ -33,6 +83,7 @@ struct dmul_ctx {
   int32_t* batch_status = nullptr;      // host array to fill at dmul_sync
   size_t batch_count = 0;
   dmi::BatchEngine* batch = nullptr;
+  dmi::Profiler* prof = nullptr;
   std::mutex mu;
 };
 

@@ -54,18 +54,26 @@ struct TwiddleSet {
 // root-table block: tables for l = 1, 2, ... are stored back to back.
 __host__ __device__ constexpr size_t root_table_offset(int l) { return ((size_t)1 << (l - 1)) - 1; }
 
+// Optional per-kernel timing: when set, a launch wrapper records an event on
+// the stream after each kernel it launches (phase ids below).
+enum Phase { kFwdCols = 0, kFwdRows, kInvRows, kInvCols, kRecLocal, kRecBlocks, kRecApply, kNumPhases };
+struct Marks {
+  virtual void mark(int phase, hipStream_t st) = 0;
+  virtual ~Marks() = default;
+};
+
 // Launch wrappers (ntt.hip, carry.hip).  All enqueue on `stream` and return
 // hipSuccess or the launch error.
 hipError_t launch_forward(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
                           const DivTable* dt, const uint64_t* a, const uint64_t* b, bool square,
                           uint64_t* bufs /* 4*N words: X1 X2 Y1 Y2 */,
-                          int* status, hipStream_t stream);
+                          int* status, hipStream_t stream, Marks* marks);
 hipError_t launch_inverse(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
-                          uint64_t* bufs, bool square, hipStream_t stream);
+                          uint64_t* bufs, bool square, hipStream_t stream, Marks* marks);
 hipError_t launch_recover(const PlanDev& pl, const Consts& cs, const DivTable* dt,
                           const uint64_t* res1,
                           const uint64_t* res2, uint64_t* out, uint64_t* scratch,
-                          hipStream_t stream);
+                          hipStream_t stream, Marks* marks);
 size_t recover_scratch_words(const PlanDev& pl);
 hipError_t launch_zero(uint64_t* out, size_t n, hipStream_t stream);
 

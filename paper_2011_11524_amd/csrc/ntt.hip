@@ -365,7 +365,7 @@ static hipError_t inv_cols_l(const PlanDev& pl, const Consts& cs, const TwiddleS
 
 hipError_t launch_forward(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
                           const DivTable* dt, const uint64_t* a, const uint64_t* b, bool square,
-                          uint64_t* bufs, int* status, hipStream_t st) {
+                          uint64_t* bufs, int* status, hipStream_t st, Marks* marks) {
   hipError_t e = hipErrorInvalidValue;
   switch (pl.logR) {
 #define X(l) case l: e = fwd_cols_l<l>(pl, cs, tw, dt, a, b, square, bufs, status, st); break;
@@ -374,16 +374,19 @@ hipError_t launch_forward(const PlanDev& pl, const Consts& cs, const TwiddleSet&
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
+  if (marks) marks->mark(kFwdCols, st);
   switch (pl.logC) {
-#define X(l) case l: return rows_l<l, false>(pl, cs, tw, bufs, square, st);
+#define X(l) case l: e = rows_l<l, false>(pl, cs, tw, bufs, square, st); break;
     DMUL_LEN_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;
   }
+  if (e == hipSuccess && marks) marks->mark(kFwdRows, st);
+  return e;
 }
 
 hipError_t launch_inverse(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
-                          uint64_t* bufs, bool square, hipStream_t st) {
+                          uint64_t* bufs, bool square, hipStream_t st, Marks* marks) {
   hipError_t e = hipErrorInvalidValue;
   switch (pl.logC) {
 #define X(l) case l: e = rows_l<l, true>(pl, cs, tw, bufs, square, st); break;
@@ -392,12 +395,15 @@ hipError_t launch_inverse(const PlanDev& pl, const Consts& cs, const TwiddleSet&
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
+  if (marks) marks->mark(kInvRows, st);
   switch (pl.logR) {
-#define X(l) case l: return inv_cols_l<l>(pl, cs, tw, bufs, st);
+#define X(l) case l: e = inv_cols_l<l>(pl, cs, tw, bufs, st); break;
     DMUL_LEN_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;
   }
+  if (e == hipSuccess && marks) marks->mark(kInvCols, st);
+  return e;
 }
 
 }  // namespace dmi
