@@ -62,8 +62,7 @@ def phase_work(N: int, logR: int, logC: int, arrays_fwd: int, NP: int, na: int, 
     w["fwd_rows"] = (arrays_fwd * fwd_stage(logC), arrays_fwd * 16 * N)
     w["inv_rows"] = (2 * (N * OPS_MODMUL + inv_stage(logC)), 2 * 24 * N)
     w["inv_cols"] = (2 * (2 * N * OPS_MODMUL + inv_stage(logR)), 2 * 16 * N)
-    w["rec_local"] = (NP * OPS_CRT, 24 * NP)
-    w["rec_blocks"] = (0, 0)
+    w["rec_crt"] = (NP * OPS_CRT, 24 * NP)
     w["rec_apply"] = (NP * OPS_CARRY, 8 * NP + 8 * (na + nb))
     return w
 

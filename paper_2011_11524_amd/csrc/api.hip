@@ -248,6 +248,35 @@ int ensure_status(dmul_ctx* ctx, size_t n) {
   return DMUL_OK;
 }
 
+// Counter and epoch-tagged map words for `nblk` recovery workgroups.  The
+// words start zeroed (epoch 0 is never used) and are cleared again when the
+// epoch wraps, so a word left by an earlier launch never matches.
+int recover_sync(dmul_ctx* ctx, size_t nblk, int* status, RecoverSync* rs) {
+  if (ctx->rec_sync_cap < nblk + 1) {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return from_hip(e);
+    if (ctx->rec_sync) (void)hipFree(ctx->rec_sync);
+    ctx->rec_sync = nullptr;
+    ctx->rec_sync_cap = 0;
+    const size_t cap = nblk + 1 > 4096 ? nblk + 1 : 4096;
+    e = hipMalloc(&ctx->rec_sync, cap * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(ctx->rec_sync, 0, cap * sizeof(uint32_t));
+    if (e != hipSuccess) return from_hip(e);
+    ctx->rec_sync_cap = cap;
+    ctx->rec_epoch = 0;
+  }
+  if (ctx->rec_epoch >= kMaxEpoch) {
+    hipError_t e = hipMemsetAsync(ctx->rec_sync + 1, 0, (ctx->rec_sync_cap - 1) * sizeof(uint32_t), ctx->stream);
+    if (e != hipSuccess) return from_hip(e);
+    ctx->rec_epoch = 0;
+  }
+  rs->epoch = ++ctx->rec_epoch;
+  rs->counter = ctx->rec_sync;
+  rs->maps = ctx->rec_sync + 1;
+  rs->status = status;
+  return DMUL_OK;
+}
+
 static bool overlaps(const uint64_t* x, size_t nx, const uint64_t* y, size_t ny) {
   if (!nx || !ny) return false;
   const uintptr_t a0 = (uintptr_t)x, a1 = a0 + nx * 8, b0 = (uintptr_t)y, b1 = b0 + ny * 8;
@@ -284,8 +313,11 @@ int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t*
     e = hipMemcpyAsync(residues, ctx->ws, 2 * pl.N * sizeof(uint64_t), hipMemcpyDeviceToDevice, ctx->stream);
     return from_hip(e);
   }
-  e = launch_recover(pl, ctx->cs, ctx->d_div, ctx->ws, ctx->ws + pl.N, out, ctx->ws + 2 * pl.N, ctx->stream,
-                     marks);
+  RecoverSync rs;
+  rc = recover_sync(ctx, recover_blocks(pl), status, &rs);
+  if (rc) return rc;
+  e = launch_recover(pl, ctx->cs, ctx->d_div, ctx->ws, ctx->ws + pl.N, out, ctx->ws + 2 * pl.N, rs,
+                     ctx->stream, marks);
   return from_hip(e);
 }
 
@@ -393,6 +425,7 @@ int dmul_ctx_create(dmul_ctx** out, int device, size_t budget) {
   if (e == hipSuccess) e = hipMemcpy(c->d_div, &dt, sizeof(DivTable), hipMemcpyHostToDevice);
   if (e != hipSuccess) rc = from_hip(e);
   if (!rc) rc = ensure_status(c, 64);
+
   if (rc) {
     dmul_ctx_destroy(c);
     return rc;
@@ -412,6 +445,7 @@ int dmul_ctx_destroy(dmul_ctx* c) {
   if (c->d_roots) (void)hipFree(c->d_roots);
   if (c->d_div) (void)hipFree(c->d_div);
   if (c->d_status) (void)hipFree(c->d_status);
+  if (c->rec_sync) (void)hipFree(c->rec_sync);
   delete c;
   return DMUL_OK;
 }
@@ -447,10 +481,12 @@ int dmul_sync(dmul_ctx* c) {
   e = hipMemcpy(st.data(), c->d_status, n * sizeof(int), hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemset(c->d_status, 0, n * sizeof(int));
   if (e != hipSuccess) return from_hip(e);
-  if (st[0] && rc == DMUL_OK) rc = DMUL_EDIGIT;
+  // status bits: 1 = a limb >= 10^19, 2 = a device-side wait gave up
+  auto code = [](int w) { return (w & 2) ? DMUL_EDEVICE : ((w & 1) ? DMUL_EDIGIT : DMUL_OK); };
+  if (st[0] && rc == DMUL_OK) rc = code(st[0]);
   if (c->batch_status) {
     for (size_t i = 0; i < c->batch_count; ++i)
-      if (st[1 + i] && c->batch_status[i] == DMUL_OK) c->batch_status[i] = DMUL_EDIGIT;
+      if (st[1 + i] && c->batch_status[i] == DMUL_OK) c->batch_status[i] = code(st[1 + i]);
   }
   c->batch_status = nullptr;
   c->batch_count = 0;
@@ -532,7 +568,7 @@ int dmul_ctx_profile_read(dmul_ctx* c, double* total_ms, uint64_t* launches, int
 
 const char* dmul_phase_name(int phase) {
   static const char* names[kNumPhases] = {"fwd_cols", "fwd_rows", "inv_rows", "inv_cols",
-                                          "rec_local", "rec_blocks", "rec_apply"};
+                                          "rec_crt", "rec_apply"};
   return (phase >= 0 && phase < kNumPhases) ? names[phase] : "unknown";
 }
 

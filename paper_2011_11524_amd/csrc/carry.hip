@@ -17,6 +17,8 @@
 // The 128-by-64-bit divisions by B use a precomputed reciprocal (Moller and
 // Granlund, "Improved division by invariant integers", 2011, the 2-by-1
 // division), the division-by-constant idea of Section 8.2.1.
+#include <stdlib.h>
+
 #include "internal.hpp"
 
 namespace dmi {
@@ -24,8 +26,6 @@ namespace dmi {
 typedef unsigned __int128 u128;
 
 constexpr int kRecThreads = 256;
-constexpr int kRecPT = 8;                          // positions per thread
-constexpr int kRecBlock = kRecThreads * kRecPT;    // positions per workgroup
 
 struct RecConsts {
   Prime P2;
@@ -36,17 +36,31 @@ struct RecConsts {
   uint64_t v;          // floor((2^128 - 1) / d) - 2^64
   int sh;
   int k;
+  uint32_t kinv;       // ceil(2^22 / k): d0 / k = (d0 * kinv) >> 22 for d0 < 2^17
+  uint32_t nblk;
+  uint32_t epoch;      // tag of this launch in the map words (24 bits, never 0)
   uint64_t NP;         // n + m coefficient positions
   uint64_t nout;       // output limbs (na + nb)
 };
 
-// (u1:u0) / d for normalised d and u1 < d.
+// 64x64 -> 128-bit product from four v_mad_u64_u32.
+__device__ __forceinline__ void mul_wide(uint64_t x, uint64_t y, uint64_t& lo, uint64_t& hi) {
+  const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
+  const uint32_t y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32);
+  const uint64_t t0 = mad_u64_u32(x0, y0, 0);
+  const uint64_t t1 = mad_u64_u32(x0, y1, t0 >> 32);
+  const uint64_t t2 = mad_u64_u32(x1, y0, (uint32_t)t1);
+  hi = mad_u64_u32(x1, y1, (t1 >> 32) + (t2 >> 32));
+  lo = (t2 << 32) | (uint32_t)t0;
+}
+
+// (u1:u0) / d for normalised d and u1 < d: quotient q < 2^64, remainder r.
 __device__ __forceinline__ void div_2by1(uint64_t u1, uint64_t u0, uint64_t d, uint64_t v,
                                          uint64_t& q, uint64_t& r) {
-  u128 qq = (u128)v * u1;
-  qq += ((u128)u1 << 64) | u0;
-  uint64_t q1 = (uint64_t)(qq >> 64) + 1;
-  const uint64_t q0 = (uint64_t)qq;
+  uint64_t q0, q1;
+  mul_wide(v, u1, q0, q1);
+  q0 += u0;
+  q1 += u1 + (q0 < u0 ? 1 : 0) + 1;
   uint64_t rr = u0 - q1 * d;
   if (rr > q0) { q1 -= 1; rr += d; }
   if (rr >= d) { q1 += 1; rr -= d; }
@@ -54,30 +68,26 @@ __device__ __forceinline__ void div_2by1(uint64_t u1, uint64_t u0, uint64_t d, u
   r = rr;
 }
 
-// x = q*B + r for a 128-bit x; returns r, writes q.
-__device__ __forceinline__ uint64_t divmod_B(u128 x, const RecConsts& rc, u128& q) {
-  const uint64_t lo = (uint64_t)x, hi = (uint64_t)(x >> 64);
-  const int sh = rc.sh;
-  const uint64_t u2 = sh ? hi >> (64 - sh) : 0;
-  const uint64_t u1 = sh ? (hi << sh) | (lo >> (64 - sh)) : hi;
-  const uint64_t u0 = lo << sh;
-  uint64_t qh, qlo, r1, r0;
-  div_2by1(u2, u1, rc.d, rc.v, qh, r1);
-  div_2by1(r1, u0, rc.d, rc.v, qlo, r0);
-  q = ((u128)qh << 64) | qlo;
-  return r0 >> sh;
-}
-
-// The base-B digits (q0, q1, q2) of coefficient c_i from its residues.
+// Base-B digits (q0, q1, q2) of coefficient c_i from its two residues:
+// CRT, then c = (q2*B + q1)*B + q0 by three 2-by-1 divisions.
 __device__ __forceinline__ void crt_digits(uint64_t a1, uint64_t a2, const RecConsts& rc,
                                            uint64_t& q0, uint64_t& q1, uint64_t& q2) {
-  const uint64_t psi = a2 >= a1 ? a2 - a1 : a2 + (rc.P2.p - a1);
-  const uint64_t phi = mont_mul(psi, rc.r_tilde, rc.P2);
-  const u128 c = (u128)rc.p1 * phi + a1;
-  u128 t, u;
-  q0 = divmod_B(c, rc, t);
-  q1 = divmod_B(t, rc, u);
-  q2 = (uint64_t)u;
+  const uint64_t psi = sub_mod(a2, a1, rc.P2);              // a1 < p1 < p2
+  const uint64_t phi = mont_mul(psi, rc.r_tilde, rc.P2);    // r * (a2 - a1) mod p2
+  uint64_t lo, hi;
+  mul_wide(rc.p1, phi, lo, hi);
+  lo += a1;
+  hi += lo < a1 ? 1 : 0;                                    // c = a1 + p1*phi < p1*p2
+  const int sh = rc.sh;                                     // 4 <= sh <= 20
+  uint64_t qh, ql, r1, r0;
+  div_2by1(hi >> (64 - sh), (hi << sh) | (lo >> (64 - sh)), rc.d, rc.v, qh, r1);
+  div_2by1(r1, lo << sh, rc.d, rc.v, ql, r0);
+  q0 = r0 >> sh;
+  // (qh:ql) = c div B < B^2: its quotient by B fits one word
+  uint64_t t, r2;
+  div_2by1((qh << sh) | (ql >> (64 - sh)), ql << sh, rc.d, rc.v, t, r2);
+  q1 = r2 >> sh;
+  q2 = t;
 }
 
 // Carry maps {0,1,2} -> {0,1,2}, two bits per image: bits [2c, 2c+2) = f(c).
@@ -106,8 +116,9 @@ __device__ __forceinline__ uint32_t compose(uint32_t later, uint32_t earlier) {
 // position order).  Returns the map of everything before this thread;
 // *total receives the map of the whole workgroup.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t f, uint32_t* total) {
-  __shared__ uint32_t wave_tot[kRecThreads / 64];
+  __shared__ uint32_t wave_tot[16];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
   uint32_t inc = f;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -116,146 +127,177 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t f, uint32_t* t
   }
   uint32_t exc = __shfl_up(inc, 1, 64);
   if (lane == 0) exc = kIdentityMap;
-  if (lane == 63) wave_tot[wid] = inc;
+  // the last active lane of each wavefront holds the wavefront's map
+  const int last = (wid == nw - 1) ? ((blockDim.x - 1) & 63) : 63;
+  if (lane == last) wave_tot[wid] = inc;
   __syncthreads();
   uint32_t before = kIdentityMap;
   for (int w = 0; w < wid; ++w) before = compose(wave_tot[w], before);
   uint32_t all = kIdentityMap;
-  for (int w = 0; w < kRecThreads / 64; ++w) all = compose(wave_tot[w], all);
+  for (int w = 0; w < nw; ++w) all = compose(wave_tot[w], all);
   *total = all;
   return compose(exc, before);
 }
 
-// Pass 1: CRT digits, s_i, per-workgroup carry map.
-__global__ void __launch_bounds__(kRecThreads)
-k_rec_local(RecConsts rc, const uint64_t* __restrict__ res1, const uint64_t* __restrict__ res2,
-            uint64_t* __restrict__ s_out, uint32_t* __restrict__ block_map) {
-  __shared__ uint64_t tail_q1[kRecThreads], tail_q2a[kRecThreads], tail_q2b[kRecThreads];
-  const uint64_t base = (uint64_t)blockIdx.x * kRecBlock + (uint64_t)threadIdx.x * kRecPT;
-  uint64_t q0[kRecPT], q1[kRecPT], q2[kRecPT];
-#pragma unroll
-  for (int u = 0; u < kRecPT; ++u) {
-    const uint64_t i = base + u;
-    if (i < rc.NP) crt_digits(res1[i], res2[i], rc, q0[u], q1[u], q2[u]);
-    else { q0[u] = q1[u] = q2[u] = 0; }
-  }
-  // q1 of the previous position and q2 of the two previous positions
-  tail_q1[threadIdx.x] = q1[kRecPT - 1];
-  tail_q2a[threadIdx.x] = q2[kRecPT - 1];
-  tail_q2b[threadIdx.x] = q2[kRecPT - 2];
-  __syncthreads();
-  uint64_t pq1, pq2_1, pq2_2;   // q1[i-1], q2[i-1], q2[i-2] for the thread's first position
-  if (threadIdx.x > 0) {
-    pq1 = tail_q1[threadIdx.x - 1];
-    pq2_1 = tail_q2a[threadIdx.x - 1];
-    pq2_2 = tail_q2b[threadIdx.x - 1];
-  } else {
-    uint64_t a0, a1v, a2v, b0, b1v, b2v;
-    if (base >= 1) crt_digits(res1[base - 1], res2[base - 1], rc, a0, a1v, a2v);
-    else a0 = a1v = a2v = 0;
-    if (base >= 2) crt_digits(res1[base - 2], res2[base - 2], rc, b0, b1v, b2v);
-    else b0 = b1v = b2v = 0;
-    pq1 = a1v;
-    pq2_1 = a2v;
-    pq2_2 = b2v;
-  }
-  uint32_t f = kIdentityMap;
-#pragma unroll
-  for (int u = 0; u < kRecPT; ++u) {
-    const uint64_t prev_q1 = u >= 1 ? q1[u - 1] : pq1;
-    const uint64_t prev2_q2 = u >= 2 ? q2[u - 2] : (u == 1 ? pq2_1 : pq2_2);
-    const uint64_t s = q0[u] + prev_q1 + prev2_q2;
-    const uint64_t i = base + u;
-    if (i < rc.NP) {
-      s_out[i] = s;
-      f = compose(carry_map(s, rc.B), f);
-    }
-  }
-  uint32_t total;
-  block_exclusive_scan(f, &total);
-  if (threadIdx.x == 0) block_map[blockIdx.x] = total;
-}
-
-// Pass 2: carry into every workgroup, cin[0] = 0, cin[b+1] = map_b(cin[b]).
-// One workgroup: each thread folds a contiguous chunk of maps, the chunk
-// maps are scanned, then each chunk is replayed to emit its carries.
-__global__ void __launch_bounds__(kRecThreads)
-k_rec_blocks(const uint32_t* __restrict__ block_map, uint32_t* __restrict__ block_cin, uint32_t nb) {
-  const uint32_t per = (nb + kRecThreads - 1) / kRecThreads;
-  const uint32_t lo = threadIdx.x * per;
-  const uint32_t hi = lo + per < nb ? lo + per : nb;
-  uint32_t f = kIdentityMap;
-  for (uint32_t b = lo; b < hi; ++b) f = compose(block_map[b], f);
-  uint32_t total;
-  const uint32_t before = block_exclusive_scan(f, &total);
-  uint32_t c = apply_map(before, 0);
-  for (uint32_t b = lo; b < hi; ++b) {
-    block_cin[b] = c;
-    c = apply_map(block_map[b], c);
-  }
-}
-
-// Pass 3: apply carries, z_i = (s_i + cin_i) mod B, then regroup the
-// workgroup's base-10^k digits into the base-10^19 limbs that start in it.
 __device__ __forceinline__ uint64_t div_p10(uint64_t x, int e, const DivTable* __restrict__ dt) {
   if (e == 0) return x;
   return __umul64hi(x >> e, dt->mag[e]) >> dt->sh[e];
 }
 
+__device__ __forceinline__ void map_store(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t map_load(uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Pass 1: CRT digits, s_i = q0_i + q1_(i-1) + q2_(i-2), and the carry map of
+// every workgroup's positions.  Thread 0 takes the four positions before the
+// workgroup (their q1, q2 feed its first s values), threads 1..256 take four
+// positions each; the digits are computed branch-free so the four
+// independent chains of a thread interleave.  The workgroup that finishes
+// last (a counter taken after a device-scope fence) scans the maps of all
+// workgroups and writes each one's incoming carry: no workgroup ever waits
+// for another.
+template <int PT>
+__global__ void __launch_bounds__(kRecThreads + 1)
+k_rec_crt(RecConsts rc, const uint64_t* __restrict__ res1, const uint64_t* __restrict__ res2,
+          uint64_t* __restrict__ s_out, uint32_t* maps, uint32_t* __restrict__ cins,
+          uint32_t* counter, int* status) {
+  constexpr int BLK = kRecThreads * PT;
+  __shared__ uint64_t tail_q1[kRecThreads + 1], tail_q2a[kRecThreads + 1], tail_q2b[kRecThreads + 1];
+  __shared__ uint32_t s_last;
+  // positions base .. base+PT-1 (thread 0: the PT positions before the workgroup)
+  const int64_t base = (int64_t)blockIdx.x * BLK + ((int64_t)threadIdx.x - 1) * PT;
+  uint64_t a1[PT], a2[PT];
+#pragma unroll
+  for (int u = 0; u < PT; ++u) {
+    const int64_t i = base + u;
+    const bool in = i >= 0 && (uint64_t)i < rc.NP;
+    a1[u] = in ? res1[i] : 0;
+    a2[u] = in ? res2[i] : 0;
+  }
+  uint64_t q0[PT], q1[PT], q2[PT];
+#pragma unroll
+  for (int u = 0; u < PT; ++u) crt_digits(a1[u], a2[u], rc, q0[u], q1[u], q2[u]);
+  tail_q1[threadIdx.x] = q1[PT - 1];
+  tail_q2a[threadIdx.x] = q2[PT - 1];
+  tail_q2b[threadIdx.x] = q2[PT - 2];
+  __syncthreads();
+  uint32_t f = kIdentityMap;
+  if (threadIdx.x > 0) {
+    const uint64_t pq1 = tail_q1[threadIdx.x - 1];
+    const uint64_t pq2_1 = tail_q2a[threadIdx.x - 1];
+    const uint64_t pq2_2 = tail_q2b[threadIdx.x - 1];
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const uint64_t prev_q1 = u >= 1 ? q1[u - 1] : pq1;
+      const uint64_t prev2_q2 = u >= 2 ? q2[u - 2] : (u == 1 ? pq2_1 : pq2_2);
+      const uint64_t sv = q0[u] + prev_q1 + prev2_q2;
+      if ((uint64_t)(base + u) < rc.NP) {
+        s_out[base + u] = sv;
+        f = compose(carry_map(sv, rc.B), f);
+      }
+    }
+  }
+  uint32_t total;
+  block_exclusive_scan(f, &total);
+  if (threadIdx.x == 0) {
+    map_store(&maps[blockIdx.x], (rc.epoch << 8) | total);
+    const uint32_t done = atomicAdd(counter, 1u);
+    s_last = done == rc.nblk - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  // The last workgroup: exclusive scan over all workgroup maps.  Every map
+  // word carries this launch's epoch, so a word is used only once its store
+  // is visible here -- no fence needed; the wait is bounded.
+  const uint32_t nb = rc.nblk;
+  const uint32_t nth = blockDim.x;
+  const uint32_t per = (nb + nth - 1) / nth;
+  const uint32_t lo = threadIdx.x * per;
+  const uint32_t hi = lo + per < nb ? lo + per : nb;
+  uint32_t g = kIdentityMap;
+  for (uint32_t b = lo; b < hi; ++b) {
+    uint32_t w = map_load(&maps[b]);
+    for (uint32_t polls = 0; (w >> 8) != rc.epoch; ++polls) {
+      if (polls > (1u << 20)) { atomicOr(status, 2); break; }
+      __builtin_amdgcn_s_sleep(1);
+      w = map_load(&maps[b]);
+    }
+    g = compose(w & 63u, g);
+  }
+  uint32_t all;
+  const uint32_t before = block_exclusive_scan(g, &all);
+  uint32_t c = apply_map(before, 0);
+  for (uint32_t b = lo; b < hi; ++b) {
+    cins[b] = c;
+    c = apply_map(map_load(&maps[b]) & 63u, c);
+  }
+  if (threadIdx.x == 0) atomicExch(counter, 0u);   // every workgroup has counted: reset
+}
+
+// Pass 2: z_i = (s_i + carry_i) mod B from the workgroup's incoming carry and
+// a scan of its maps, then the base-10^19 limbs whose first digit lies in
+// the workgroup's digit range (digits of the two positions after it are
+// included: a limb may end there).
+template <int PT>
 __global__ void __launch_bounds__(kRecThreads)
-k_rec_apply(RecConsts rc, const DivTable* __restrict__ dt, const uint64_t* __restrict__ s_in,
-            const uint32_t* __restrict__ block_map, const uint32_t* __restrict__ block_cin,
-            uint64_t* __restrict__ out) {
-  __shared__ uint64_t z[kRecBlock + 2];
-  const uint64_t bbase = (uint64_t)blockIdx.x * kRecBlock;
-  const uint64_t base = bbase + (uint64_t)threadIdx.x * kRecPT;
+k_rec_apply(RecConsts rc, const DivTable* __restrict__ dt_g, const uint64_t* __restrict__ s_in,
+            const uint32_t* __restrict__ cins, uint64_t* __restrict__ out) {
+  constexpr int BLK = kRecThreads * PT;
+  __shared__ uint64_t z[BLK + 2];
+  __shared__ DivTable sdt;
+  for (unsigned i = threadIdx.x; i < sizeof(DivTable) / 4; i += blockDim.x)
+    reinterpret_cast<uint32_t*>(&sdt)[i] = reinterpret_cast<const uint32_t*>(dt_g)[i];
+  const DivTable* dt = &sdt;
+  const uint64_t bbase = (uint64_t)blockIdx.x * BLK;
+  const uint64_t base = bbase + (uint64_t)threadIdx.x * PT;
   const uint64_t B = rc.B;
-  uint64_t s[kRecPT];
+  uint64_t s[PT];
   uint32_t f = kIdentityMap;
 #pragma unroll
-  for (int u = 0; u < kRecPT; ++u) {
+  for (int u = 0; u < PT; ++u) {
     const uint64_t i = base + u;
     s[u] = i < rc.NP ? s_in[i] : 0;
     if (i < rc.NP) f = compose(carry_map(s[u], B), f);
   }
   uint32_t total;
   const uint32_t before = block_exclusive_scan(f, &total);
-  const uint32_t cin_block = block_cin[blockIdx.x];
-  uint32_t c = apply_map(before, cin_block);
+  uint32_t c = apply_map(before, cins[blockIdx.x]);
 #pragma unroll
-  for (int u = 0; u < kRecPT; ++u) {
+  for (int u = 0; u < PT; ++u) {
     uint64_t t = s[u] + c;
     uint32_t o = 0;
     if (t >= B) { t -= B; o = 1; }
     if (t >= B) { t -= B; o = 2; }
-    z[threadIdx.x * kRecPT + u] = t;
+    z[threadIdx.x * PT + u] = t;
     c = o;
   }
-  // two digits past the block end (needed by limbs that start here)
-  if (threadIdx.x == 0) {
-    uint32_t cc = apply_map(total, cin_block);
+  if (threadIdx.x == kRecThreads - 1) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const uint64_t i = bbase + kRecBlock + u;
-      uint64_t t = i < rc.NP ? s_in[i] + cc : 0;
+      const uint64_t i = bbase + BLK + u;
+      uint64_t t = (i < rc.NP ? s_in[i] : 0) + c;
       uint32_t o = 0;
       if (t >= B) { t -= B; o = 1; }
       if (t >= B) { t -= B; o = 2; }
-      z[kRecBlock + u] = t;
-      cc = o;
+      z[BLK + u] = t;
+      c = o;
     }
   }
   __syncthreads();
-  // limbs j with first digit 19j in [k*bbase, k*(bbase + kRecBlock))
+
+  // limbs j with first digit 19j in [k*bbase, k*(bbase + BLK))
   const uint64_t k = (uint64_t)rc.k;
-  const uint64_t d_lo = k * bbase, d_hi = k * (bbase + kRecBlock);
+  const uint64_t d_lo = k * bbase, d_hi = k * (bbase + BLK);
   const uint64_t j_lo = (d_lo + 18) / 19;
   uint64_t j_hi = (d_hi + 18) / 19;
   if (j_hi > rc.nout) j_hi = rc.nout;
   for (uint64_t j = j_lo + threadIdx.x; j < j_hi; j += kRecThreads) {
-    const uint64_t d0 = 19 * j - d_lo;          // digit offset inside the block
-    const uint64_t i0 = d0 / k;
-    const int o = (int)(d0 - i0 * k);
+    const uint32_t d0 = (uint32_t)(19 * j - d_lo);     // digit offset inside the workgroup, < 2^17
+    const uint32_t i0 = (uint32_t)(((uint64_t)d0 * rc.kinv) >> 22);
+    const int o = (int)(d0 - i0 * (uint32_t)rc.k);
     const int have0 = rc.k - o;
     uint64_t limb = div_p10(z[i0], o, dt);
     const int need = 19 - have0;
@@ -277,15 +319,20 @@ __global__ void k_zero(uint64_t* __restrict__ out, size_t n) {
     out[i] = 0;
 }
 
+constexpr int kRecPT = 4;
+constexpr int kRecBlock = kRecThreads * kRecPT;    // positions per workgroup
+
+size_t recover_blocks(const PlanDev& pl) {
+  return (size_t)((pl.n + pl.m + kRecBlock - 1) / kRecBlock);
+}
+
 size_t recover_scratch_words(const PlanDev& pl) {
-  const uint64_t NP = pl.n + pl.m;
-  const uint64_t nblk = (NP + kRecBlock - 1) / kRecBlock;
-  return NP + nblk;   // s (u64 per position) + two u32 per block
+  return (size_t)(pl.n + pl.m) + recover_blocks(pl) + 1;   // s, then carries (u32)
 }
 
 hipError_t launch_recover(const PlanDev& pl, const Consts& cs, const DivTable* dt,
                           const uint64_t* res1, const uint64_t* res2, uint64_t* out,
-                          uint64_t* scratch, hipStream_t st, Marks* marks) {
+                          uint64_t* scratch, const RecoverSync& sync, hipStream_t st, Marks* marks) {
   RecConsts rc;
   rc.P2 = cs.P[1];
   rc.p1 = cs.P[0].p;
@@ -296,17 +343,17 @@ hipError_t launch_recover(const PlanDev& pl, const Consts& cs, const DivTable* d
   rc.sh = __builtin_clzll(rc.B);
   rc.d = rc.B << rc.sh;
   rc.v = (uint64_t)((~(u128)0) / rc.d - ((u128)1 << 64));
+  rc.kinv = (uint32_t)(((1u << 22) + pl.k - 1) / pl.k);
   rc.NP = pl.n + pl.m;
   rc.nout = pl.na + pl.nb;
-  const uint64_t nblk = (rc.NP + kRecBlock - 1) / kRecBlock;
+  rc.nblk = (uint32_t)recover_blocks(pl);
+  rc.epoch = sync.epoch;
   uint64_t* s = scratch;
-  uint32_t* maps = (uint32_t*)(scratch + rc.NP);
-  uint32_t* cins = maps + nblk;
-  hipLaunchKernelGGL(k_rec_local, dim3((unsigned)nblk), dim3(kRecThreads), 0, st, rc, res1, res2, s, maps);
-  if (marks) marks->mark(kRecLocal, st);
-  hipLaunchKernelGGL(k_rec_blocks, dim3(1), dim3(kRecThreads), 0, st, maps, cins, (uint32_t)nblk);
-  if (marks) marks->mark(kRecBlocks, st);
-  hipLaunchKernelGGL(k_rec_apply, dim3((unsigned)nblk), dim3(kRecThreads), 0, st, rc, dt, s, maps, cins, out);
+  uint32_t* cins = (uint32_t*)(scratch + rc.NP);
+  hipLaunchKernelGGL(k_rec_crt<kRecPT>, dim3(rc.nblk), dim3(kRecThreads + 1), 0, st, rc, res1, res2, s,
+                     sync.maps, cins, sync.counter, sync.status);
+  if (marks) marks->mark(kRecCrt, st);
+  hipLaunchKernelGGL(k_rec_apply<kRecPT>, dim3(rc.nblk), dim3(kRecThreads), 0, st, rc, dt, s, cins, out);
   if (marks) marks->mark(kRecApply, st);
   return hipGetLastError();
 }

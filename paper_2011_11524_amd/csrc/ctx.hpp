@@ -84,6 +84,9 @@ struct dmul_ctx {
   size_t batch_count = 0;
   dmi::BatchEngine* batch = nullptr;
   dmi::Profiler* prof = nullptr;
+  uint32_t* rec_sync = nullptr;         // recovery: [0] counter, [1..] map words
+  size_t rec_sync_cap = 0;
+  uint32_t rec_epoch = 0;
   std::mutex mu;
 };
 
@@ -92,6 +95,7 @@ int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl);
 size_t workspace_words(const PlanDev& pl);
 int get_twiddles(dmul_ctx* ctx, int logN, int logR, TwiddleSet* tw);
 int ensure_workspace(dmul_ctx* ctx, size_t words);
+int recover_sync(dmul_ctx* ctx, size_t nblk, int* status, RecoverSync* rs);
 int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
                     uint64_t* out, unsigned flags, int* status, uint64_t* residues);
 }  // namespace dmi

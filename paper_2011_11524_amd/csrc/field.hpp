@@ -5,18 +5,19 @@
 // n >= 32, Section 4.5), and p < 2^63 = mu/2 with mu = 2^64 (eq. pi_bound).
 //
 // Multiplication is Montgomery's REDC(x, y) = x*y*R^-1 mod p with R = 2^64
-// (Section 4.4.3).  Because p == 1 (mod 2^32), -p^-1 == -1 (mod 2^32) and the
-// reduction by 2^64 runs as two 32-bit word-serial rounds, each
-//     m = -t mod 2^32;   t = (t + m*p) / 2^32
-// costing one 32x32->64 multiply by p_hi: there is no multiply by p'.
-// The full product takes four v_mad_u64_u32; the reduction two more.
+// (Section 4.4.3), in its signed form: with m = T * p^-1 mod 2^64 the
+// value (T - m*p) / 2^64 is exact and lies in (-p, p), so one conditional
+// +p makes it canonical.  Because p == 1 (mod 2^32), p^-1 == 1 - p_hi*2^32
+// (mod 2^64): m needs one 32x32 product (m = (T0, T1 - lo(T0*p_hi))) and
+// floor(m*p / 2^64) one more, so the reduction is two v_mad_u64_u32 on top
+// of the four of the 64x64->128 product, with no multiply by a p'.
 //
 // REDC accepts one operand "unadjusted" in [0, 2p) and the other in [0, p):
-// then x*y < 2p^2 < mu*p, the input range of MontgomeryReduce (Section 8.3).
-// Every result leaves here canonical in [0, p).
+// then x*y < 2p^2 < mu*p (Section 8.3), floor(x*y / 2^64) < p and the
+// result stays in (-p, p).  Every result leaves here canonical in [0, p).
 //
-// Additions and subtractions are branch-free selects (Section 8.1): the
-// compiler emits v_cndmask, never a branch.
+// Additions and subtractions are branch-free (Section 8.1): the borrow of a
+// 64-bit subtraction selects the corrected value (v_cndmask).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -36,38 +37,50 @@ __device__ __forceinline__ uint64_t mad_u64_u32(uint32_t a, uint32_t b, uint64_t
 __device__ __forceinline__ uint64_t mont_mul(uint64_t x, uint64_t y, const Prime& P) {
   const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
   const uint32_t y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32);
-  // 128-bit product T = t3*2^64 + lo(t2)*2^32 + lo(t0)
+  // T = x*y = Thi*2^64 + T1*2^32 + T0
   const uint64_t t0 = mad_u64_u32(x0, y0, 0);
   const uint64_t t1 = mad_u64_u32(x0, y1, t0 >> 32);
   const uint64_t t2 = mad_u64_u32(x1, y0, (uint32_t)t1);
-  const uint64_t t3 = mad_u64_u32(x1, y1, (t1 >> 32) + (t2 >> 32));
-  // round 1: m1 = -T0; (T + m1*p)/2^32 = u + t3*2^32, u = m1*p_hi + T1 + [T0 != 0]
-  const uint32_t T0 = (uint32_t)t0;
-  const uint32_t m1 = 0u - T0;
-  const uint64_t u = mad_u64_u32(m1, P.p_hi, (uint64_t)(uint32_t)t2 + (uint64_t)(T0 != 0u));
-  const uint64_t V = t3 + (u >> 32);
-  // round 2: m2 = -lo(u); result = m2*p_hi + V + [lo(u) != 0]  (< 2p)
-  const uint32_t U0 = (uint32_t)u;
-  const uint32_t m2 = 0u - U0;
-  const uint64_t r = mad_u64_u32(m2, P.p_hi, V + (uint64_t)(U0 != 0u));
-  return r >= P.p ? r - P.p : r;
+  const uint64_t t3 = mad_u64_u32(x1, y1, t1 >> 32);
+  unsigned c, c2;
+  const uint32_t th_lo = __builtin_addc((uint32_t)t3, (uint32_t)(t2 >> 32), 0u, &c);
+  const uint32_t th_hi = __builtin_addc((uint32_t)(t3 >> 32), 0u, c, &c2);
+  const uint32_t T0 = (uint32_t)t0, T1 = (uint32_t)t2;
+  // m = (T0, T1 - lo(T0*p_hi));  floor(m*p / 2^64) = m1*p_hi + hi(T0*p_hi) + borrow
+  const uint64_t h = mad_u64_u32(T0, P.p_hi, 0);
+  unsigned bw, unused;
+  const uint32_t m1 = __builtin_subc(T1, (uint32_t)h, 0u, &bw);
+  const uint32_t hh = __builtin_addc((uint32_t)(h >> 32), 0u, bw, &unused);
+  const uint64_t mp = mad_u64_u32(m1, P.p_hi, (uint64_t)hh);
+  // r = Thi - floor(m*p / 2^64), in (-p, p)
+  unsigned b1, b2;
+  const uint32_t r_lo = __builtin_subc(th_lo, (uint32_t)mp, 0u, &b1);
+  const uint32_t r_hi = __builtin_subc(th_hi, (uint32_t)(mp >> 32), b1, &b2);
+  const uint64_t r = ((uint64_t)r_hi << 32) | r_lo;
+  return b2 ? r + P.p : r;
 }
 
 // x + y mod p for x, y < p
 __device__ __forceinline__ uint64_t add_mod(uint64_t x, uint64_t y, const Prime& P) {
   const uint64_t s = x + y;
-  return s >= P.p ? s - P.p : s;
+  unsigned b1, b2;
+  const uint32_t d_lo = __builtin_subc((uint32_t)s, (uint32_t)P.p, 0u, &b1);
+  const uint32_t d_hi = __builtin_subc((uint32_t)(s >> 32), (uint32_t)(P.p >> 32), b1, &b2);
+  return b2 ? s : (((uint64_t)d_hi << 32) | d_lo);
 }
 
 // x - y mod p for x, y < p
 __device__ __forceinline__ uint64_t sub_mod(uint64_t x, uint64_t y, const Prime& P) {
-  const uint64_t d = x - y;
-  return x >= y ? d : d + P.p;
+  unsigned b1, b2;
+  const uint32_t d_lo = __builtin_subc((uint32_t)x, (uint32_t)y, 0u, &b1);
+  const uint32_t d_hi = __builtin_subc((uint32_t)(x >> 32), (uint32_t)(y >> 32), b1, &b2);
+  const uint64_t d = ((uint64_t)d_hi << 32) | d_lo;
+  return b2 ? d + P.p : d;
 }
 
 // x - y + p in [1, 2p): the unadjusted difference, a valid REDC operand.
 __device__ __forceinline__ uint64_t sub_lazy(uint64_t x, uint64_t y, const Prime& P) {
-  return x + (P.p - y);
+  return (x - y) + P.p;
 }
 
 }  // namespace dmi

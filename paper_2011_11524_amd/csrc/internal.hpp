@@ -56,7 +56,7 @@ __host__ __device__ constexpr size_t root_table_offset(int l) { return ((size_t)
 
 // Optional per-kernel timing: when set, a launch wrapper records an event on
 // the stream after each kernel it launches (phase ids below).
-enum Phase { kFwdCols = 0, kFwdRows, kInvRows, kInvCols, kRecLocal, kRecBlocks, kRecApply, kNumPhases };
+enum Phase { kFwdCols = 0, kFwdRows, kInvRows, kInvCols, kRecCrt, kRecApply, kNumPhases };
 struct Marks {
   virtual void mark(int phase, hipStream_t st) = 0;
   virtual ~Marks() = default;
@@ -70,10 +70,22 @@ hipError_t launch_forward(const PlanDev& pl, const Consts& cs, const TwiddleSet&
                           int* status, hipStream_t stream, Marks* marks);
 hipError_t launch_inverse(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
                           uint64_t* bufs, bool square, hipStream_t stream, Marks* marks);
+// Answer recovery: `scratch` holds recover_scratch_words() words (s_i, then
+// per-workgroup carries).  The map words live in a buffer only the
+// recovery kernel writes, tagged with a per-launch epoch (24 bits, never
+// 0); `counter` is zero between launches; `status` receives bit 2 if a wait
+// for a map word gave up.
+struct RecoverSync {
+  uint32_t* maps;
+  uint32_t* counter;
+  int* status;
+  uint32_t epoch;
+};
+constexpr uint32_t kMaxEpoch = (1u << 24) - 1;
 hipError_t launch_recover(const PlanDev& pl, const Consts& cs, const DivTable* dt,
-                          const uint64_t* res1,
-                          const uint64_t* res2, uint64_t* out, uint64_t* scratch,
-                          hipStream_t stream, Marks* marks);
+                          const uint64_t* res1, const uint64_t* res2, uint64_t* out,
+                          uint64_t* scratch, const RecoverSync& sync, hipStream_t stream, Marks* marks);
+size_t recover_blocks(const PlanDev& pl);
 size_t recover_scratch_words(const PlanDev& pl);
 hipError_t launch_zero(uint64_t* out, size_t n, hipStream_t stream);
 

@@ -25,6 +25,8 @@
 // together with N^-1, by the scale R^2 N^-1 folded into the inverse
 // inter-pass table (the linearity trick, Section 6, merged with the
 // twiddle as Section 7.9 suggests).
+#include <stdlib.h>
+
 #include "internal.hpp"
 
 namespace dmi {
@@ -63,12 +65,19 @@ struct Round {
     return lowF | (jl << LO_B) | (highF << (LO_B + NB));
   }
 
-  static __device__ __forceinline__ void run(uint64_t* lds, const uint64_t* __restrict__ tw,
-                                             const Prime& P, int t) {
-    constexpr int E = G::E;
-    uint64_t v[E];
+  static __device__ __forceinline__ void load(const uint64_t* lds, uint64_t (&v)[G::E], int t) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = lds[lds_pos<LOGE>(index(t, j))];
+    for (int j = 0; j < G::E; ++j) v[j] = lds[lds_pos<LOGE>(index(t, j))];
+  }
+  static __device__ __forceinline__ void store(uint64_t* lds, const uint64_t (&v)[G::E], int t) {
+#pragma unroll
+    for (int j = 0; j < G::E; ++j) lds[lds_pos<LOGE>(index(t, j))] = v[j];
+  }
+
+  // The butterflies of the round on the thread's registers.
+  static __device__ __forceinline__ void compute(uint64_t (&v)[G::E], const uint64_t* __restrict__ tw,
+                                                 const Prime& P, int t) {
+    constexpr int E = G::E;
 #pragma unroll
     for (int s = 0; s < NB; ++s) {
       const int lb = DIT ? s : (NB - 1 - s);   // local bit of this stage
@@ -98,8 +107,14 @@ struct Round {
         }
       }
     }
-#pragma unroll
-    for (int j = 0; j < E; ++j) lds[lds_pos<LOGE>(index(t, j))] = v[j];
+  }
+
+  static __device__ __forceinline__ void run(uint64_t* lds, const uint64_t* __restrict__ tw,
+                                             const Prime& P, int t) {
+    uint64_t v[G::E];
+    load(lds, v, t);
+    compute(v, tw, P, t);
+    store(lds, v, t);
   }
 };
 
@@ -120,6 +135,27 @@ template <int LOGL, int LOGE, bool DIT>
 struct Rounds<LOGL, LOGE, DIT, (LOGL + LOGE - 1) / LOGE> {
   static __device__ __forceinline__ void run(uint64_t*, const uint64_t* __restrict__, const Prime&,
                                              int, bool) {}
+};
+
+// Bounds of round R of a DIF (top bits first) or DIT (bottom bits first) transform.
+template <int LOGL, int LOGE, bool DIT, int R>
+struct RoundBits {
+  static constexpr int LO_B = Rounds<LOGL, LOGE, DIT, R>::LO_B;
+  static constexpr int NB = Rounds<LOGL, LOGE, DIT, R>::HI_B - LO_B;
+  using type = Round<LOGL, LOGE, DIT, LO_B, NB>;
+};
+
+// Rounds [R, END) through LDS, a barrier after each.
+template <int LOGL, int LOGE, bool DIT, int R, int END>
+struct RoundRange {
+  static __device__ __forceinline__ void run(uint64_t* lds, const uint64_t* __restrict__ tw,
+                                             const Prime& P, int t) {
+    if constexpr (R < END) {
+      RoundBits<LOGL, LOGE, DIT, R>::type::run(lds, tw, P, t);
+      __syncthreads();
+      RoundRange<LOGL, LOGE, DIT, R + 1, END>::run(lds, tw, P, t);
+    }
+  }
 };
 
 // In-LDS transform of 2^LOGL points (DIF natural->bit-reversed, or DIT
@@ -178,43 +214,73 @@ __device__ __forceinline__ uint64_t pass_factor(const uint64_t* __restrict__ hi,
 
 // ---------------------------------------------------------------------------
 // Pass A, forward: split + column DIF + inter-pass factor.
-// grid.x = C / T column tiles, grid.y = 2 primes x (1 or 2) operands.
+// grid.x = C / T column tiles, grid.y = operand.  The digit groups of the
+// tile are split once, kept in registers, and transformed for each prime in
+// turn (the groups are below 10^k < p, the same residues for both primes).
+// The root tables of length R for both primes are staged in LDS.
 // ---------------------------------------------------------------------------
 template <int LOGR, int LOGE, int T>
 __global__ void __launch_bounds__((T * Geometry<LOGR, LOGE>::NT))
-k_fwd_cols(PlanDev pl, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt,
+k_fwd_cols(PlanDev pl, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g,
            const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
            uint64_t* __restrict__ bufs, int* status) {
   using G = Geometry<LOGR, LOGE>;
+  constexpr int R = G::L;
+  constexpr int NTH = T * G::NT;                 // threads
+  constexpr int PER = (R * T + NTH - 1) / NTH;   // tile points per thread
   extern __shared__ uint64_t lds[];
-  const int y = blockIdx.y;
-  const int pi = y & 1, op = y >> 1;
-  const Prime P = cs.P[pi];
+  uint64_t* troots = lds + T * G::STRIDE;        // [prime][R/2]
+  const int op = blockIdx.y;
   const uint64_t* src = op ? b : a;
   const uint64_t nl = op ? pl.nb : pl.na;
   const uint64_t ng = op ? pl.m : pl.n;
-  uint64_t* dst = bufs + (size_t)y * pl.N;
   const uint64_t C = (uint64_t)1 << pl.logC;
   const uint64_t j0 = (uint64_t)blockIdx.x * T;
-  constexpr int R = G::L;
+  __shared__ DivTable sdt;
+  for (unsigned i = threadIdx.x; i < sizeof(DivTable) / 4; i += blockDim.x)
+    reinterpret_cast<uint32_t*>(&sdt)[i] = reinterpret_cast<const uint32_t*>(dt_g)[i];
+  const DivTable* dt = &sdt;
 
-  for (int q = threadIdx.x; q < R * T; q += blockDim.x) {
-    const int row = q / T, col = q % T;
-    uint64_t v = 0;
-    if (j0 + col < C) v = split_group(src, nl, ng, (uint64_t)row * C + j0 + col, pl.k, dt, status);
-    lds[col * G::STRIDE + lds_pos<LOGE>(row)] = v;
+  for (int i = threadIdx.x; i < R; i += NTH) {
+    const int p = i / (R / 2) , e = i % (R / 2);
+    troots[i] = tw.len_fwd[p][root_table_offset(LOGR) + e];
   }
   __syncthreads();
+  for (int q = threadIdx.x; q < R * T; q += NTH) {
+    const int row = q / T, col = q % T;
+    lds[col * G::STRIDE + lds_pos<LOGE>(row)] =
+        j0 + col < C ? split_group(src, nl, ng, (uint64_t)row * C + j0 + col, pl.k, dt, status) : 0;
+  }
+  __syncthreads();
+  uint64_t v[PER];   // the split tile, kept for the second prime
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int q = threadIdx.x + s * NTH;
+    v[s] = q < R * T ? lds[(q % T) * G::STRIDE + lds_pos<LOGE>(q / T)] : 0;
+  }
   const int col = threadIdx.x / G::NT, t = threadIdx.x % G::NT;
-  lds_transform<LOGR, LOGE, false>(lds + col * G::STRIDE, tw.len_fwd[pi] + root_table_offset(LOGR),
-                                   P, t, true);
-  for (int q = threadIdx.x; q < R * T; q += blockDim.x) {
-    const int row = q / T, c = q % T;
-    if (j0 + c >= C) continue;
-    const uint64_t e = (uint64_t)bitrev(row, LOGR) * (j0 + c);
-    uint64_t v = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
-    v = mont_mul(v, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], e, pl.logC, P), P);
-    dst[(uint64_t)row * C + j0 + c] = v;
+#pragma unroll 1
+  for (int pi = 0; pi < 2; ++pi) {
+    const Prime P = cs.P[pi];
+    uint64_t* dst = bufs + (size_t)(2 * op + pi) * pl.N;
+    if (pi == 1) {
+#pragma unroll
+      for (int s = 0; s < PER; ++s) {
+        const int q = threadIdx.x + s * NTH;
+        if (q < R * T) lds[(q % T) * G::STRIDE + lds_pos<LOGE>(q / T)] = v[s];
+      }
+      __syncthreads();
+    }
+    lds_transform<LOGR, LOGE, false>(lds + col * G::STRIDE, troots + pi * (R / 2), P, t, true);
+    for (int q = threadIdx.x; q < R * T; q += NTH) {
+      const int row = q / T, c = q % T;
+      if (j0 + c >= C) continue;
+      const uint64_t e = (uint64_t)bitrev(row, LOGR) * (j0 + c);
+      uint64_t x = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
+      x = mont_mul(x, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], e, pl.logC, P), P);
+      dst[(uint64_t)row * C + j0 + c] = x;
+    }
+    __syncthreads();
   }
 }
 
@@ -222,38 +288,83 @@ k_fwd_cols(PlanDev pl, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt
 // Pass B: row transforms.  Forward: DIF in place on every row of every
 // (operand, prime) buffer.  Inverse: pointwise REDC(X, Y) then DIT, written
 // over X.
+//
+// grid.y selects the buffer (forward: prime + 2*operand; inverse: prime);
+// the workgroups along x loop over groups of RPW rows of that buffer.  A
+// thread holds points t + j*NT of its row (j < E): that
+// is the coalesced layout of the global loads, the first DIF round (top
+// bits) runs on it without an LDS round trip, and the last DIT round ends
+// in it and is stored straight to global memory.  With TWL the row
+// length's root table is staged in LDS once per workgroup.
 // ---------------------------------------------------------------------------
-template <int LOGC, int LOGE, int RPW, bool INV>
+template <int LOGC, int LOGE, int RPW, bool INV, bool TWL>
 __global__ void __launch_bounds__((RPW * Geometry<LOGC, LOGE>::NT))
 k_rows(PlanDev pl, Consts cs, TwiddleSet tw, uint64_t* __restrict__ bufs, int square) {
   using G = Geometry<LOGC, LOGE>;
+  constexpr int C = G::L, E = G::E, NT = G::NT;
+  constexpr int NR = G::ROUNDS;
   extern __shared__ uint64_t lds[];
-  constexpr int C = G::L;
   const int y = blockIdx.y;
   const int pi = y & 1;
   const Prime P = cs.P[pi];
   uint64_t* X = bufs + (size_t)y * pl.N;                       // inverse: y = prime
   const uint64_t* Y = bufs + (size_t)(square ? pi : 2 + pi) * pl.N;
   const uint64_t R = (uint64_t)1 << pl.logR;
-  const uint64_t r0 = (uint64_t)blockIdx.x * RPW;
+  const uint32_t groups = (uint32_t)((R + RPW - 1) / RPW);
+  const int r = threadIdx.x / NT, t = threadIdx.x % NT;
+  uint64_t* row_lds = lds + r * G::STRIDE;
 
-  for (int q = threadIdx.x; q < C * RPW; q += blockDim.x) {
-    const int r = q / C, c = q % C;
-    uint64_t v = 0;
-    if (r0 + r < R) {
-      const uint64_t gi = (r0 + r) * C + c;
-      v = X[gi];
-      if (INV) v = mont_mul(v, Y[gi], P);
-    }
-    lds[r * G::STRIDE + lds_pos<LOGE>(c)] = v;
+  const uint64_t* roots_g = (INV ? tw.len_inv[pi] : tw.len_fwd[pi]) + root_table_offset(LOGC);
+  const uint64_t* roots = roots_g;
+  if constexpr (TWL) {
+    uint64_t* tl = lds + RPW * G::STRIDE;
+    for (int i = threadIdx.x; i < C / 2; i += blockDim.x) tl[i] = roots_g[i];
+    roots = tl;
   }
-  __syncthreads();
-  const int r = threadIdx.x / G::NT, t = threadIdx.x % G::NT;
-  const uint64_t* roots = (INV ? tw.len_inv[pi] : tw.len_fwd[pi]) + root_table_offset(LOGC);
-  lds_transform<LOGC, LOGE, INV>(lds + r * G::STRIDE, roots, P, t, true);
-  for (int q = threadIdx.x; q < C * RPW; q += blockDim.x) {
-    const int rr = q / C, c = q % C;
-    if (r0 + rr < R) X[(r0 + rr) * C + c] = lds[rr * G::STRIDE + lds_pos<LOGE>(c)];
+
+  uint64_t cur[E];
+  if constexpr (TWL) __syncthreads();
+  for (uint32_t g = blockIdx.x; g < groups; g += gridDim.x) {
+    const uint64_t row = (uint64_t)g * RPW + r;
+    if (row < R) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        cur[j] = X[row * C + t + j * NT];
+        if (INV) cur[j] = mont_mul(cur[j], Y[row * C + t + j * NT], P);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < E; ++j) cur[j] = 0;
+    }
+    if constexpr (!INV) {
+      // round 0 (top bits) straight from the loaded registers
+      using R0 = typename RoundBits<LOGC, LOGE, false, 0>::type;
+      R0::compute(cur, roots, P, t);
+      R0::store(row_lds, cur, t);
+      __syncthreads();
+      RoundRange<LOGC, LOGE, false, 1, NR>::run(row_lds, roots, P, t);
+      // points back to the coalesced layout
+#pragma unroll
+      for (int j = 0; j < E; ++j) cur[j] = row_lds[lds_pos<LOGE>(t + j * NT)];
+      if (row < R) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) X[row * C + t + j * NT] = cur[j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < E; ++j) row_lds[lds_pos<LOGE>(t + j * NT)] = cur[j];
+      __syncthreads();
+      RoundRange<LOGC, LOGE, true, 0, NR - 1>::run(row_lds, roots, P, t);
+      // last round (top bits) ends in the coalesced layout
+      using RL = typename RoundBits<LOGC, LOGE, true, NR - 1>::type;
+      RL::load(row_lds, cur, t);
+      RL::compute(cur, roots, P, t);
+      if (row < R) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) X[row * C + RL::index(t, j)] = cur[j];
+      }
+    }
+    __syncthreads();   // the next group reuses the LDS rows
   }
 }
 
@@ -266,6 +377,7 @@ __global__ void __launch_bounds__((T * Geometry<LOGR, LOGE>::NT))
 k_inv_cols(PlanDev pl, Consts cs, TwiddleSet tw, uint64_t* __restrict__ bufs) {
   using G = Geometry<LOGR, LOGE>;
   extern __shared__ uint64_t lds[];
+  uint64_t* troots = lds + T * G::STRIDE;
   const int pi = blockIdx.y;
   const Prime P = cs.P[pi];
   uint64_t* X = bufs + (size_t)pi * pl.N;
@@ -273,6 +385,8 @@ k_inv_cols(PlanDev pl, Consts cs, TwiddleSet tw, uint64_t* __restrict__ bufs) {
   const uint64_t j0 = (uint64_t)blockIdx.x * T;
   constexpr int R = G::L;
 
+  for (int i = threadIdx.x; i < R / 2; i += blockDim.x)
+    troots[i] = tw.len_inv[pi][root_table_offset(LOGR) + i];
   for (int q = threadIdx.x; q < R * T; q += blockDim.x) {
     const int row = q / T, c = q % T;
     uint64_t v = 0;
@@ -285,8 +399,7 @@ k_inv_cols(PlanDev pl, Consts cs, TwiddleSet tw, uint64_t* __restrict__ bufs) {
   }
   __syncthreads();
   const int col = threadIdx.x / G::NT, t = threadIdx.x % G::NT;
-  lds_transform<LOGR, LOGE, true>(lds + col * G::STRIDE, tw.len_inv[pi] + root_table_offset(LOGR),
-                                  P, t, true);
+  lds_transform<LOGR, LOGE, true>(lds + col * G::STRIDE, troots, P, t, true);
   for (int q = threadIdx.x; q < R * T; q += blockDim.x) {
     const int row = q / T, c = q % T;
     if (j0 + c < C) X[(uint64_t)row * C + j0 + c] = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
@@ -297,11 +410,16 @@ k_inv_cols(PlanDev pl, Consts cs, TwiddleSet tw, uint64_t* __restrict__ bufs) {
 // Launch configuration and dispatch over the compile-time lengths.
 // ---------------------------------------------------------------------------
 constexpr int loge_for(int logl) { return logl < 4 ? logl : 4; }
-constexpr int cols_per_tile(int logl) {
-  // about 512 threads per workgroup, at most 64 columns
-  return (512 >> (logl - loge_for(logl))) < 1 ? 1
-         : ((512 >> (logl - loge_for(logl))) > 64 ? 64 : (512 >> (logl - loge_for(logl))));
+// Columns per tile for a target workgroup size (at most 64 columns).  The
+// forward column pass keeps the split tile in registers for its second
+// prime, so it runs smaller workgroups (256 threads) to fit three per CU;
+// the inverse one runs 512.
+constexpr int cols_for_threads(int logl, int threads) {
+  return (threads >> (logl - loge_for(logl))) < 1 ? 1
+         : ((threads >> (logl - loge_for(logl))) > 64 ? 64 : (threads >> (logl - loge_for(logl))));
 }
+constexpr int cols_per_tile(int logl) { return cols_for_threads(logl, 512); }
+constexpr int fwd_cols_per_tile(int logl) { return cols_for_threads(logl, 256); }
 constexpr int rows_per_wg(int logl) {
   return (256 >> (logl - loge_for(logl))) < 1 ? 1 : (256 >> (logl - loge_for(logl)));
 }
@@ -318,32 +436,58 @@ template <int LOGR>
 static hipError_t fwd_cols_l(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
                              const DivTable* dt, const uint64_t* a, const uint64_t* b, bool square,
                              uint64_t* bufs, int* status, hipStream_t st) {
-  constexpr int LOGE = loge_for(LOGR), T = cols_per_tile(LOGR);
+  constexpr int LOGE = loge_for(LOGR), T = fwd_cols_per_tile(LOGR);
   using G = Geometry<LOGR, LOGE>;
-  const size_t lds = (size_t)T * G::STRIDE * sizeof(uint64_t);
+  const size_t lds = ((size_t)T * G::STRIDE + (size_t)G::L) * sizeof(uint64_t);
   auto kern = k_fwd_cols<LOGR, LOGE, T>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
   const uint64_t C = (uint64_t)1 << pl.logC;
-  dim3 grid((unsigned)((C + T - 1) / T), square ? 2 : 4);
+  dim3 grid((unsigned)((C + T - 1) / T), square ? 1 : 2);
   hipLaunchKernelGGL(kern, grid, dim3(T * G::NT), lds, st, pl, cs, tw, dt, a, b, bufs, status);
+  return hipGetLastError();
+}
+
+// Tuning knobs of the row pass (read once from the environment, for
+// experiments): DMUL_ROWS_TWL=1 stages root tables in LDS, DMUL_ROWS_ITERS
+// is the number of row groups each workgroup loops over.
+struct RowTuning {
+  int twl = 1;
+  int iters = 1;
+};
+static RowTuning row_tuning() {
+  static RowTuning rt = [] {
+    RowTuning t;
+    if (const char* e = getenv("DMUL_ROWS_TWL")) t.twl = atoi(e);
+    if (const char* e = getenv("DMUL_ROWS_ITERS")) t.iters = atoi(e) > 0 ? atoi(e) : 1;
+    return t;
+  }();
+  return rt;
+}
+
+template <int LOGC, bool INV, bool TWL>
+static hipError_t rows_launch(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
+                              uint64_t* bufs, bool square, hipStream_t st) {
+  constexpr int LOGE = loge_for(LOGC), RPW = rows_per_wg(LOGC);
+  using G = Geometry<LOGC, LOGE>;
+  const size_t lds = ((size_t)RPW * G::STRIDE + (TWL ? (size_t)G::L / 2 : 0)) * sizeof(uint64_t);
+  auto kern = k_rows<LOGC, LOGE, RPW, INV, TWL>;
+  hipError_t e = prepare(kern, lds);
+  if (e != hipSuccess) return e;
+  const uint64_t R = (uint64_t)1 << pl.logR;
+  const uint64_t groups = (R + RPW - 1) / RPW;
+  const int iters = row_tuning().iters;
+  const unsigned gx = (unsigned)((groups + iters - 1) / iters);
+  const unsigned ny = INV ? 2 : (square ? 2 : 4);
+  hipLaunchKernelGGL(kern, dim3(gx, ny), dim3(RPW * G::NT), lds, st, pl, cs, tw, bufs, square ? 1 : 0);
   return hipGetLastError();
 }
 
 template <int LOGC, bool INV>
 static hipError_t rows_l(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw, uint64_t* bufs,
                          bool square, hipStream_t st) {
-  constexpr int LOGE = loge_for(LOGC), RPW = rows_per_wg(LOGC);
-  using G = Geometry<LOGC, LOGE>;
-  const size_t lds = (size_t)RPW * G::STRIDE * sizeof(uint64_t);
-  auto kern = k_rows<LOGC, LOGE, RPW, INV>;
-  hipError_t e = prepare(kern, lds);
-  if (e != hipSuccess) return e;
-  const uint64_t R = (uint64_t)1 << pl.logR;
-  const unsigned ny = INV ? 2 : (square ? 2 : 4);
-  dim3 grid((unsigned)((R + RPW - 1) / RPW), ny);
-  hipLaunchKernelGGL(kern, grid, dim3(RPW * G::NT), lds, st, pl, cs, tw, bufs, square ? 1 : 0);
-  return hipGetLastError();
+  if (row_tuning().twl) return rows_launch<LOGC, INV, true>(pl, cs, tw, bufs, square, st);
+  return rows_launch<LOGC, INV, false>(pl, cs, tw, bufs, square, st);
 }
 
 template <int LOGR>
@@ -351,7 +495,7 @@ static hipError_t inv_cols_l(const PlanDev& pl, const Consts& cs, const TwiddleS
                              uint64_t* bufs, hipStream_t st) {
   constexpr int LOGE = loge_for(LOGR), T = cols_per_tile(LOGR);
   using G = Geometry<LOGR, LOGE>;
-  const size_t lds = (size_t)T * G::STRIDE * sizeof(uint64_t);
+  const size_t lds = ((size_t)T * G::STRIDE + (size_t)G::L / 2) * sizeof(uint64_t);
   auto kern = k_inv_cols<LOGR, LOGE, T>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
