@@ -103,35 +103,46 @@ def cpu_baseline(a, b, budget_s: float, max_products: int):
     return out, times
 
 
-def run_batched(dm, ctx, torch, steps: int, warmup: int, count: int):
-    """The batched workload (4096 products, operand lengths log-uniform in
-    [10^3, 10^6] digits, aspect ratio in [1, 4]) as one dmul_batch against
-    one dmul_ex per product."""
+def _pct(xs, q):
     import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else None
+
+
+def run_batched(dm, ctx, torch, steps: int, warmup: int, count: int):
+    """The batched workload: `count` products, operand lengths log-uniform in
+    [10^3, 10^6] digits with an aspect ratio uniform in [1, 4], uniform
+    digits; one dmul_batch (one launch per phase and size class) against one
+    dmul_ex per product.  Throughput from K timed repetitions; completion
+    latency of every product (from the first kernel of the batch, events on
+    the launch stream) from one profiled repetition of each mode."""
+    import numpy as np
+    import oracle
     import synth
     da, db = synth.batched_lengths(count)
-    rng = np.random.default_rng(4005)
     pool = synth.OperandPool(10 ** 6, seed=4006, pool_limbs=4 * synth.limbs_for_digits(10 ** 6))
-    pairs, outs, digits = [], [], 0
+    host, pairs, outs_a, outs_b, digits = [], [], [], [], 0
     for x, y in zip(da, db):
         a = pool.take(int(x))
         b = pool.take(int(y))
-        ta, tb = dm.to_device(a), dm.to_device(b)
-        pairs.append((ta, tb))
-        outs.append(torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda"))
+        host.append((a, b))
+        pairs.append((dm.to_device(a), dm.to_device(b)))
+        outs_a.append(torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda"))
+        outs_b.append(torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda"))
         digits += int(x) + int(y)
-    del rng
+    logn = [dm.plan(len(a), len(b)).log2_n for a, b in host]
 
     def one_by_one():
-        for (ta, tb), o in zip(pairs, outs):
+        for (ta, tb), o in zip(pairs, outs_a):
             ctx.mul_async(ta, tb, o)
         ctx.sync()
 
     def batched():
-        ctx.batch_async(pairs, outs)
+        st = ctx.batch_async(pairs, outs_b)
         ctx.sync()
+        return st
 
-    res = {}
+    res = {"products": count, "digits": digits,
+           "size_classes": {int(k): int(v) for k, v in zip(*np.unique(logn, return_counts=True))}}
     for name, fn in (("per_product", one_by_one), ("batched", batched)):
         for _ in range(warmup):
             fn()
@@ -142,9 +153,27 @@ def run_batched(dm, ctx, torch, steps: int, warmup: int, count: int):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         res[name] = {"ms_per_batch": dt * 1e3, "digits_per_s": digits / dt}
-    res["products"] = count
-    res["digits"] = digits
+    # completion latency of every product, one profiled repetition per mode
+    ctx.profile(True)
+    one_by_one()
+    ev = [t for ph, t in ctx.profile_events() if ph == "rec_apply"]
+    lat_pp = ev[:count]
+    batched()
+    ev = [t for ph, t in ctx.profile_events() if ph == "rec_apply"]
+    ctx.profile(False)
+    classes = sorted(set(logn))
+    done = {c: ev[i] for i, c in enumerate(classes)} if len(ev) == len(classes) else {}
+    lat_b = [done[c] for c in logn] if done else []
+    for name, lat in (("per_product", lat_pp), ("batched", lat_b)):
+        res[name]["p50_ms"] = _pct(lat, 50)
+        res[name]["p99_ms"] = _pct(lat, 99)
     res["speedup"] = res["per_product"]["ms_per_batch"] / res["batched"]["ms_per_batch"]
+    # every batched result equals its per-product result; a sample against the oracle
+    same = all(torch.equal(x, y) for x, y in zip(outs_a, outs_b))
+    rng = np.random.default_rng(4007)
+    sample = rng.choice(count, size=min(12, count), replace=False)
+    ok = all(np.array_equal(outs_b[i].cpu().numpy(), oracle.mul_ntt(*host[i])) for i in sample)
+    res["parity"] = "bit-exact" if (same and ok) else "MISMATCH"
     return res
 
 
@@ -260,7 +289,8 @@ def main() -> int:
     }
 
     if args.batched:
-        result["batched"] = run_batched(dm, ctx, torch, max(1, args.steps // 10), 1, args.batch_count)
+        result["batched"] = run_batched(dm, ctx, torch, max(2, args.steps // 5), 1, args.batch_count)
+        print(f"[bench] batched: {json.dumps(result['batched'])}", flush=True)
 
     if not args.no_cpu_baseline:
         want, times = cpu_baseline(a, b, args.cpu_budget, 3)

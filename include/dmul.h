@@ -155,6 +155,11 @@ int dmul_debug_residues(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint6
  * "rec_apply"). */
 int dmul_ctx_profile(dmul_ctx* ctx, int enable);
 int dmul_ctx_profile_read(dmul_ctx* ctx, double* total_ms, uint64_t* launches, int n);
+/* The kernels of the work completed by the last dmul_sync, in launch order:
+ * phases[i] and end_ms[i] = the end of kernel i in milliseconds after the
+ * first event of that work (profiling must be on).  Returns the number of
+ * kernels (fills at most n). */
+int dmul_ctx_profile_events(dmul_ctx* ctx, int32_t* phases, double* end_ms, int n);
 const char* dmul_phase_name(int phase);
 
 /* Library version string. */

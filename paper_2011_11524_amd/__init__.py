@@ -33,7 +33,7 @@ DMUL_EDEVICE = -5
 EXPORTS = ("dmul", "dmul_ctx_create", "dmul_ctx_destroy", "dmul_ctx_set_stream", "dmul_ex",
            "dmul_sync", "dmul_batch", "dmul_plan", "dmul_workspace_bytes", "dmul_strerror",
            "dmul_host", "dmul_primes", "dmul_debug_residues", "dmul_version", "dmul_ctx_profile",
-           "dmul_ctx_profile_read", "dmul_phase_name")
+           "dmul_ctx_profile_read", "dmul_phase_name", "dmul_ctx_profile_events")
 
 
 class DmulError(RuntimeError):
@@ -101,6 +101,8 @@ def lib():
     L.dmul_ctx_profile.argtypes = [vp, ctypes.c_int]
     L.dmul_ctx_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
+    L.dmul_ctx_profile_events.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     L.dmul_phase_name.argtypes = [ctypes.c_int]
     L.dmul_phase_name.restype = ctypes.c_char_p
     _lib = L
@@ -252,6 +254,17 @@ class Context:
         if got < 0:
             raise DmulError(got, "dmul_ctx_profile_read")
         return {self._lib.dmul_phase_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(got)}
+
+    def profile_events(self):
+        """[(phase name, end ms)] of every kernel of the work completed by the
+        last sync, in launch order."""
+        n = self._lib.dmul_ctx_profile_events(self._h, None, None, 0)
+        if n <= 0:
+            return []
+        ph = (ctypes.c_int32 * n)()
+        t = (ctypes.c_double * n)()
+        self._lib.dmul_ctx_profile_events(self._h, ph, t, n)
+        return [(self._lib.dmul_phase_name(ph[i]).decode(), float(t[i])) for i in range(n)]
 
     # -- debug view of the convolution ---------------------------------------
     def residues(self, a, b, force_k: int = 0):

@@ -8,9 +8,15 @@
 // Every step of a product runs in the kernels of ntt.hip and carry.hip.
 #include <dmul.h>
 
+#include <dlfcn.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "batch.hpp"
@@ -106,12 +112,13 @@ bool check_div_table(const DivTable& t) {
   return true;
 }
 
-int from_hip(hipError_t e) { return e == hipSuccess ? DMUL_OK : (e == hipErrorOutOfMemory ? DMUL_ENOMEM : DMUL_EDEVICE); }
 
 }  // namespace
 
 
 namespace dmi {
+
+int from_hip(hipError_t e) { return e == hipSuccess ? DMUL_OK : (e == hipErrorOutOfMemory ? DMUL_ENOMEM : DMUL_EDEVICE); }
 
 int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl) {
   if (flags & ~DMUL_FLAG_K_MASK) return DMUL_EINVAL;
@@ -248,33 +255,26 @@ int ensure_status(dmul_ctx* ctx, size_t n) {
   return DMUL_OK;
 }
 
-// Counter and epoch-tagged map words for `nblk` recovery workgroups.  The
-// words start zeroed (epoch 0 is never used) and are cleared again when the
-// epoch wraps, so a word left by an earlier launch never matches.
-int recover_sync(dmul_ctx* ctx, size_t nblk, int* status, RecoverSync* rs) {
-  if (ctx->rec_sync_cap < nblk + 1) {
-    hipError_t e = hipStreamSynchronize(ctx->stream);
-    if (e != hipSuccess) return from_hip(e);
-    if (ctx->rec_sync) (void)hipFree(ctx->rec_sync);
-    ctx->rec_sync = nullptr;
-    ctx->rec_sync_cap = 0;
-    const size_t cap = nblk + 1 > 4096 ? nblk + 1 : 4096;
-    e = hipMalloc(&ctx->rec_sync, cap * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemset(ctx->rec_sync, 0, cap * sizeof(uint32_t));
-    if (e != hipSuccess) return from_hip(e);
-    ctx->rec_sync_cap = cap;
-    ctx->rec_epoch = 0;
-  }
-  if (ctx->rec_epoch >= kMaxEpoch) {
-    hipError_t e = hipMemsetAsync(ctx->rec_sync + 1, 0, (ctx->rec_sync_cap - 1) * sizeof(uint32_t), ctx->stream);
-    if (e != hipSuccess) return from_hip(e);
-    ctx->rec_epoch = 0;
-  }
-  rs->epoch = ++ctx->rec_epoch;
-  rs->counter = ctx->rec_sync;
-  rs->maps = ctx->rec_sync + 1;
-  rs->status = status;
+// Recovery sync words (a counter and one map word per workgroup) for at
+// least `words` words; zeroed at allocation and left zeroed by every launch.
+int ensure_rec_sync(dmul_ctx* ctx, size_t words) {
+  if (ctx->rec_sync_cap >= words) return DMUL_OK;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return from_hip(e);
+  if (ctx->rec_sync) (void)hipFree(ctx->rec_sync);
+  ctx->rec_sync = nullptr;
+  ctx->rec_sync_cap = 0;
+  const size_t cap = words > 4096 ? words : 4096;
+  e = hipMalloc(&ctx->rec_sync, cap * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(ctx->rec_sync, 0, cap * sizeof(uint32_t));
+  if (e != hipSuccess) return from_hip(e);
+  ctx->rec_sync_cap = cap;
   return DMUL_OK;
+}
+
+int row_iters_for(const dmul_ctx* ctx, int logN) {
+  if (logN >= 0 && logN <= kMaxLogN && ctx->tune.row_iters[logN] > 0) return ctx->tune.row_iters[logN];
+  return 1;
 }
 
 static bool overlaps(const uint64_t* x, size_t nx, const uint64_t* y, size_t ny) {
@@ -303,22 +303,62 @@ int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t*
   if (rc) return rc;
   rc = ensure_workspace(ctx, workspace_words(pl));
   if (rc) return rc;
-  const bool square = (a == b && na == nb);
+  rc = ensure_rec_sync(ctx, recover_blocks(pl) + 1);
+  if (rc) return rc;
+  Work w{};
+  ProdDesc& d = w.one;
+  d.pl = pl;
+  d.a = a;
+  d.b = b;
+  d.out = out;
+  d.ws = ctx->ws;
+  d.status = status;
+  d.rec_sync = ctx->rec_sync;
+  d.nblk = (uint32_t)recover_blocks(pl);
+  d.square = (a == b && na == nb) ? 1 : 0;
+  w.many = nullptr;
+  w.count = 1;
+  Shape sh{pl.logR, pl.logC, d.square ? 0 : 1, row_iters_for(ctx, pl.logN), d.nblk};
   Marks* marks = ctx->prof;
   if (ctx->prof) ctx->prof->begin(ctx->stream);
-  hipError_t e = launch_forward(pl, ctx->cs, tw, ctx->d_div, a, b, square, ctx->ws, status, ctx->stream, marks);
-  if (e == hipSuccess) e = launch_inverse(pl, ctx->cs, tw, ctx->ws, square, ctx->stream, marks);
+  hipError_t e = launch_forward(w, sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
+  if (e == hipSuccess) e = launch_inverse(w, sh, ctx->cs, tw, ctx->stream, marks);
   if (e != hipSuccess) return from_hip(e);
   if (residues) {
     e = hipMemcpyAsync(residues, ctx->ws, 2 * pl.N * sizeof(uint64_t), hipMemcpyDeviceToDevice, ctx->stream);
     return from_hip(e);
   }
-  RecoverSync rs;
-  rc = recover_sync(ctx, recover_blocks(pl), status, &rs);
-  if (rc) return rc;
-  e = launch_recover(pl, ctx->cs, ctx->d_div, ctx->ws, ctx->ws + pl.N, out, ctx->ws + 2 * pl.N, rs,
-                     ctx->stream, marks);
+  e = launch_recover(w, sh, ctx->cs, ctx->d_div, ctx->stream, marks);
   return from_hip(e);
+}
+
+// The size-class tuning table: DMUL_TUNE_TABLE, else dmul_tune.txt next to
+// the library.  Lines "log2N row_iters" ('#' starts a comment); missing or
+// unreadable tables leave the defaults.
+void load_tuning(TuneTable* t) {
+  std::string path;
+  if (const char* e = getenv("DMUL_TUNE_TABLE")) {
+    path = e;
+  } else {
+    Dl_info info;
+    if (dladdr((void*)&load_tuning, &info) && info.dli_fname) {
+      path = info.dli_fname;
+      const size_t slash = path.rfind('/');
+      path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) + "/dmul_tune.txt";
+    }
+  }
+  if (path.empty()) return;
+  FILE* f = fopen(path.c_str(), "r");
+  if (!f) return;
+  char line[256];
+  while (fgets(line, sizeof line, f)) {
+    if (line[0] == '#') continue;
+    int logn = 0, iters = 0;
+    if (sscanf(line, "%d %d", &logn, &iters) == 2 && logn >= 0 && logn <= kMaxLogN && iters > 0 &&
+        iters <= 64)
+      t->row_iters[logn] = iters;
+  }
+  fclose(f);
 }
 
 }  // namespace dmi
@@ -394,6 +434,7 @@ int dmul_ctx_create(dmul_ctx** out, int device, size_t budget) {
   if (!c) return DMUL_ENOMEM;
   c->device = device;
   c->budget = budget;
+  load_tuning(&c->tune);
   for (int i = 0; i < 2; ++i) {
     c->cs.P[i].p = kP[i];
     c->cs.P[i].p_hi = (uint32_t)(kP[i] >> 32);
@@ -564,6 +605,18 @@ int dmul_ctx_profile_read(dmul_ctx* c, double* total_ms, uint64_t* launches, int
     launches[i] = c->prof ? c->prof->count[i] : 0;
   }
   return kNumPhases;
+}
+
+int dmul_ctx_profile_events(dmul_ctx* c, int32_t* phases, double* end_ms, int n) {
+  if (!c || n < 0 || (n && (!phases || !end_ms))) return DMUL_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!c->prof) return 0;
+  const int m = (int)c->prof->timeline.size();
+  for (int i = 0; i < n && i < m; ++i) {
+    phases[i] = c->prof->timeline[i].first;
+    end_ms[i] = c->prof->timeline[i].second;
+  }
+  return m;
 }
 
 const char* dmul_phase_name(int phase) {

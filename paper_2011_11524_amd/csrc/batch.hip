@@ -1,19 +1,149 @@
-// Batched products: every product goes through the same kernels as a
-// single product, one after another on the context's stream.
+// Batched products.  A batch is planned on the host, grouped into size
+// classes by transform length, given one workspace per product, and its
+// descriptors are copied to the device once; then each class runs as six
+// launches (forward columns and rows, inverse rows and columns, the two
+// recovery passes) covering all of its products.  A batch of P products in
+// c classes needs 6c launches instead of 6P.
 #include <dmul.h>
+
+#include <algorithm>
+#include <map>
+#include <vector>
 
 #include "batch.hpp"
 #include "ctx.hpp"
 
 namespace dmi {
 
+BatchEngine::~BatchEngine() {
+  if (ws_) (void)hipFree(ws_);
+  if (sync_) (void)hipFree(sync_);
+  if (d_desc_) (void)hipFree(d_desc_);
+  if (h_desc_) (void)hipHostFree(h_desc_);
+  if (copied_) (void)hipEventDestroy(copied_);
+}
+
+int BatchEngine::reserve(dmul_ctx* ctx, size_t ws_words, size_t sync_words, size_t ndesc) {
+  const bool grow = ws_words > ws_words_ || sync_words > sync_words_ || ndesc > desc_cap_;
+  if (!grow) return DMUL_OK;
+  if (ctx->budget && ws_words * sizeof(uint64_t) > ctx->budget) return DMUL_ENOMEM;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return from_hip(e);
+  if (ws_words > ws_words_) {
+    if (ws_) (void)hipFree(ws_);
+    ws_ = nullptr;
+    ws_words_ = 0;
+    e = hipMalloc(&ws_, ws_words * sizeof(uint64_t));
+    if (e != hipSuccess) return from_hip(e);
+    ws_words_ = ws_words;
+  }
+  if (sync_words > sync_words_) {
+    if (sync_) (void)hipFree(sync_);
+    sync_ = nullptr;
+    sync_words_ = 0;
+    e = hipMalloc(&sync_, sync_words * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(sync_, 0, sync_words * sizeof(uint32_t));
+    if (e != hipSuccess) return from_hip(e);
+    sync_words_ = sync_words;
+  }
+  if (ndesc > desc_cap_) {
+    if (d_desc_) (void)hipFree(d_desc_);
+    if (h_desc_) (void)hipHostFree(h_desc_);
+    d_desc_ = nullptr;
+    h_desc_ = nullptr;
+    desc_cap_ = 0;
+    e = hipMalloc(&d_desc_, ndesc * sizeof(ProdDesc));
+    if (e == hipSuccess) e = hipHostMalloc(&h_desc_, ndesc * sizeof(ProdDesc), hipHostMallocDefault);
+    if (e != hipSuccess) return from_hip(e);
+    desc_cap_ = ndesc;
+  }
+  return DMUL_OK;
+}
+
 int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, const size_t* na,
                      const uint64_t* const* b, const size_t* nb, uint64_t* const* out,
                      int32_t* status, unsigned flags, int* status_dev) {
+  if (!copied_) {
+    if (hipEventCreateWithFlags(&copied_, hipEventDisableTiming) != hipSuccess) return DMUL_EDEVICE;
+  }
+  // plan, and group the products by transform length
+  std::vector<PlanDev> plans(count);
+  std::map<int, std::vector<uint32_t>> classes;
+  size_t ws_words = 0, sync_words = 0, nvalid = 0;
   for (size_t i = 0; i < count; ++i) {
-    const int rc = enqueue_product(ctx, a[i], na[i], b[i], nb[i], out[i], flags, status_dev + i, nullptr);
-    if (rc) status[i] = rc;
-    if (rc == DMUL_EDEVICE) return rc;
+    if (na[i] == 0 || nb[i] == 0) {
+      const hipError_t e = launch_zero(out[i], na[i] + nb[i], ctx->stream);
+      if (e != hipSuccess) return from_hip(e);
+      continue;
+    }
+    const int rc = make_plan(na[i], nb[i], flags, &plans[i]);
+    if (rc) {
+      status[i] = rc;
+      continue;
+    }
+    classes[plans[i].logN].push_back((uint32_t)i);
+    ws_words += workspace_words(plans[i]);
+    sync_words += recover_blocks(plans[i]) + 1;
+    ++nvalid;
+  }
+  if (nvalid == 0) return DMUL_OK;
+  int rc = reserve(ctx, ws_words, sync_words, nvalid);
+  if (rc) {
+    for (auto& kv : classes)
+      for (uint32_t i : kv.second) status[i] = rc;
+    return rc == DMUL_EDEVICE ? rc : DMUL_OK;
+  }
+  // the staging buffer may still feed the previous batch's copy
+  if (hipEventSynchronize(copied_) != hipSuccess) return DMUL_EDEVICE;
+  size_t wofs = 0, sofs = 0, di = 0;
+  struct Cls { int logN; size_t first, n; Shape sh; };
+  std::vector<Cls> cls;
+  for (auto& kv : classes) {
+    Cls c{kv.first, di, kv.second.size(), {}};
+    const PlanDev& p0 = plans[kv.second[0]];
+    c.sh.logR = p0.logR;
+    c.sh.logC = p0.logC;
+    c.sh.row_iters = row_iters_for(ctx, p0.logN);
+    c.sh.any_nonsquare = 0;
+    c.sh.max_nblk = 0;
+    for (uint32_t i : kv.second) {
+      ProdDesc& d = h_desc_[di++];
+      d.pl = plans[i];
+      d.a = a[i];
+      d.b = b[i];
+      d.out = out[i];
+      d.ws = ws_ + wofs;
+      d.status = status_dev + i;
+      d.rec_sync = sync_ + sofs;
+      d.nblk = (uint32_t)recover_blocks(plans[i]);
+      d.square = (a[i] == b[i] && na[i] == nb[i]) ? 1 : 0;
+      if (!d.square) c.sh.any_nonsquare = 1;
+      c.sh.max_nblk = std::max(c.sh.max_nblk, d.nblk);
+      wofs += workspace_words(plans[i]);
+      sofs += d.nblk + 1;
+    }
+    cls.push_back(c);
+  }
+  hipError_t e = hipMemcpyAsync(d_desc_, h_desc_, nvalid * sizeof(ProdDesc), hipMemcpyHostToDevice,
+                                ctx->stream);
+  if (e == hipSuccess) e = hipEventRecord(copied_, ctx->stream);
+  if (e != hipSuccess) return from_hip(e);
+  Marks* marks = ctx->prof;
+  if (ctx->prof) ctx->prof->begin(ctx->stream);
+  for (const Cls& c : cls) {
+    TwiddleSet tw;
+    rc = get_twiddles(ctx, c.logN, c.sh.logR, &tw);
+    if (rc) return rc;
+    // grid.z is at most 65535: a very large class goes in several launches
+    for (size_t off = 0; off < c.n; off += 65535) {
+      Work w{};
+      w.many = d_desc_ + c.first + off;
+      w.count = (uint32_t)std::min<size_t>(65535, c.n - off);
+      e = launch_forward(w, c.sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
+      if (e == hipSuccess) e = launch_inverse(w, c.sh, ctx->cs, tw, ctx->stream, marks);
+      if (e == hipSuccess) e = launch_recover(w, c.sh, ctx->cs, ctx->d_div, ctx->stream, marks);
+      if (e != hipSuccess) return from_hip(e);
+    }
   }
   return DMUL_OK;
 }

@@ -1,7 +1,13 @@
-// Batched products (dmul_batch).
+// Batched products (dmul_batch): products are grouped by transform length
+// (a size class) and every phase of a class runs as one launch over all of
+// its products, each workgroup finding its product by blockIdx.z.
 #pragma once
 #include <stddef.h>
 #include <stdint.h>
+
+#include <vector>
+
+#include "internal.hpp"
 
 struct dmul_ctx;
 
@@ -9,11 +15,25 @@ namespace dmi {
 
 class BatchEngine {
  public:
+  ~BatchEngine();
   // Enqueues `count` products on the context's stream; status_dev[i] is the
-  // device word product i reports a bad limb to.
+  // device word product i reports to.  Host-side errors go to status[i].
   int run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, const size_t* na,
           const uint64_t* const* b, const size_t* nb, uint64_t* const* out, int32_t* status,
           unsigned flags, int* status_dev);
+
+ private:
+  int reserve(dmul_ctx* ctx, size_t ws_words, size_t sync_words, size_t ndesc);
+
+  uint64_t* ws_ = nullptr;          // per-product workspaces, back to back
+  size_t ws_words_ = 0;
+  uint32_t* sync_ = nullptr;        // per-product recovery sync words (kept zero)
+  size_t sync_words_ = 0;
+  ProdDesc* d_desc_ = nullptr;      // descriptors on the device
+  ProdDesc* h_desc_ = nullptr;      // pinned staging copy
+  size_t desc_cap_ = 0;
+  hipEvent_t copied_ = nullptr;     // the staging copy has been consumed
+  int device_ = -1;
 };
 
 }  // namespace dmi

@@ -27,21 +27,55 @@ typedef unsigned __int128 u128;
 
 constexpr int kRecThreads = 256;
 
+__device__ __forceinline__ ProdDesc load_desc(const Work& w) {
+  return w.many ? w.many[blockIdx.z] : w.one;
+}
+
+// Constants of the answer recovery.  Per digit-group size k (13..18):
+// B = 10^k, the normalised divisor d = B << sh with its reciprocal
+// v = floor((2^128 - 1) / d) - 2^64, and kinv = ceil(2^22 / k)
+// (d0 / k = (d0 * kinv) >> 22 for d0 < 2^17).
+struct RecTable {
+  Prime P2;
+  uint64_t p1;
+  uint64_t r_tilde;
+  uint64_t B[6], d[6], v[6];
+  uint32_t sh[6], kinv[6];
+};
+
+// What one product's recovery needs, taken from the table by its k.
 struct RecConsts {
   Prime P2;
   uint64_t p1;
   uint64_t r_tilde;
-  uint64_t B;          // 10^k
-  uint64_t d;          // B << sh (normalised divisor)
-  uint64_t v;          // floor((2^128 - 1) / d) - 2^64
+  uint64_t B;
+  uint64_t d;
+  uint64_t v;
   int sh;
   int k;
-  uint32_t kinv;       // ceil(2^22 / k): d0 / k = (d0 * kinv) >> 22 for d0 < 2^17
+  uint32_t kinv;
   uint32_t nblk;
-  uint32_t epoch;      // tag of this launch in the map words (24 bits, never 0)
   uint64_t NP;         // n + m coefficient positions
   uint64_t nout;       // output limbs (na + nb)
 };
+
+__device__ __forceinline__ RecConsts rec_consts(const RecTable& t, const ProdDesc& d) {
+  RecConsts rc;
+  const int i = d.pl.k - kMinK;
+  rc.P2 = t.P2;
+  rc.p1 = t.p1;
+  rc.r_tilde = t.r_tilde;
+  rc.B = t.B[i];
+  rc.d = t.d[i];
+  rc.v = t.v[i];
+  rc.sh = (int)t.sh[i];
+  rc.kinv = t.kinv[i];
+  rc.k = d.pl.k;
+  rc.nblk = d.nblk;
+  rc.NP = d.pl.n + d.pl.m;
+  rc.nout = d.pl.na + d.pl.nb;
+  return rc;
+}
 
 // 64x64 -> 128-bit product from four v_mad_u64_u32.
 __device__ __forceinline__ void mul_wide(uint64_t x, uint64_t y, uint64_t& lo, uint64_t& hi) {
@@ -144,6 +178,8 @@ __device__ __forceinline__ uint64_t div_p10(uint64_t x, int e, const DivTable* _
   return __umul64hi(x >> e, dt->mag[e]) >> dt->sh[e];
 }
 
+constexpr uint32_t kMapValid = 1u << 8;
+
 __device__ __forceinline__ void map_store(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -161,9 +197,17 @@ __device__ __forceinline__ uint32_t map_load(uint32_t* p) {
 // for another.
 template <int PT>
 __global__ void __launch_bounds__(kRecThreads + 1)
-k_rec_crt(RecConsts rc, const uint64_t* __restrict__ res1, const uint64_t* __restrict__ res2,
-          uint64_t* __restrict__ s_out, uint32_t* maps, uint32_t* __restrict__ cins,
-          uint32_t* counter, int* status) {
+k_rec_crt(Work w, RecTable rt) {
+  const ProdDesc d = load_desc(w);
+  if (blockIdx.x >= d.nblk) return;
+  const RecConsts rc = rec_consts(rt, d);
+  const uint64_t* __restrict__ res1 = d.ws;
+  const uint64_t* __restrict__ res2 = d.ws + d.pl.N;
+  uint64_t* __restrict__ s_out = d.ws + 2 * d.pl.N;
+  uint32_t* __restrict__ cins = (uint32_t*)(s_out + rc.NP);
+  uint32_t* maps = d.rec_sync + 1;
+  uint32_t* counter = d.rec_sync;
+  int* status = d.status;
   constexpr int BLK = kRecThreads * PT;
   __shared__ uint64_t tail_q1[kRecThreads + 1], tail_q2a[kRecThreads + 1], tail_q2b[kRecThreads + 1];
   __shared__ uint32_t s_last;
@@ -203,15 +247,16 @@ k_rec_crt(RecConsts rc, const uint64_t* __restrict__ res1, const uint64_t* __res
   uint32_t total;
   block_exclusive_scan(f, &total);
   if (threadIdx.x == 0) {
-    map_store(&maps[blockIdx.x], (rc.epoch << 8) | total);
+    map_store(&maps[blockIdx.x], kMapValid | total);
     const uint32_t done = atomicAdd(counter, 1u);
     s_last = done == rc.nblk - 1 ? 1u : 0u;
   }
   __syncthreads();
   if (!s_last) return;
-  // The last workgroup: exclusive scan over all workgroup maps.  Every map
-  // word carries this launch's epoch, so a word is used only once its store
-  // is visible here -- no fence needed; the wait is bounded.
+  // The last workgroup: exclusive scan over all workgroup maps.  A map word
+  // is used only once its valid bit is visible here (no fence needed; the
+  // wait is bounded), and the words are cleared again afterwards, so the
+  // launch leaves the buffer as it found it (and can be replayed).
   const uint32_t nb = rc.nblk;
   const uint32_t nth = blockDim.x;
   const uint32_t per = (nb + nth - 1) / nth;
@@ -219,13 +264,13 @@ k_rec_crt(RecConsts rc, const uint64_t* __restrict__ res1, const uint64_t* __res
   const uint32_t hi = lo + per < nb ? lo + per : nb;
   uint32_t g = kIdentityMap;
   for (uint32_t b = lo; b < hi; ++b) {
-    uint32_t w = map_load(&maps[b]);
-    for (uint32_t polls = 0; (w >> 8) != rc.epoch; ++polls) {
+    uint32_t mw = map_load(&maps[b]);
+    for (uint32_t polls = 0; !(mw & kMapValid); ++polls) {
       if (polls > (1u << 20)) { atomicOr(status, 2); break; }
       __builtin_amdgcn_s_sleep(1);
-      w = map_load(&maps[b]);
+      mw = map_load(&maps[b]);
     }
-    g = compose(w & 63u, g);
+    g = compose(mw & 63u, g);
   }
   uint32_t all;
   const uint32_t before = block_exclusive_scan(g, &all);
@@ -233,6 +278,7 @@ k_rec_crt(RecConsts rc, const uint64_t* __restrict__ res1, const uint64_t* __res
   for (uint32_t b = lo; b < hi; ++b) {
     cins[b] = c;
     c = apply_map(map_load(&maps[b]) & 63u, c);
+    map_store(&maps[b], 0u);
   }
   if (threadIdx.x == 0) atomicExch(counter, 0u);   // every workgroup has counted: reset
 }
@@ -243,9 +289,14 @@ k_rec_crt(RecConsts rc, const uint64_t* __restrict__ res1, const uint64_t* __res
 // included: a limb may end there).
 template <int PT>
 __global__ void __launch_bounds__(kRecThreads)
-k_rec_apply(RecConsts rc, const DivTable* __restrict__ dt_g, const uint64_t* __restrict__ s_in,
-            const uint32_t* __restrict__ cins, uint64_t* __restrict__ out) {
+k_rec_apply(Work w, RecTable rt, const DivTable* __restrict__ dt_g) {
   constexpr int BLK = kRecThreads * PT;
+  const ProdDesc d = load_desc(w);
+  if (blockIdx.x >= d.nblk) return;
+  const RecConsts rc = rec_consts(rt, d);
+  const uint64_t* __restrict__ s_in = d.ws + 2 * d.pl.N;
+  const uint32_t* __restrict__ cins = (const uint32_t*)(s_in + rc.NP);
+  uint64_t* __restrict__ out = d.out;
   __shared__ uint64_t z[BLK + 2];
   __shared__ DivTable sdt;
   for (unsigned i = threadIdx.x; i < sizeof(DivTable) / 4; i += blockDim.x)
@@ -330,30 +381,25 @@ size_t recover_scratch_words(const PlanDev& pl) {
   return (size_t)(pl.n + pl.m) + recover_blocks(pl) + 1;   // s, then carries (u32)
 }
 
-hipError_t launch_recover(const PlanDev& pl, const Consts& cs, const DivTable* dt,
-                          const uint64_t* res1, const uint64_t* res2, uint64_t* out,
-                          uint64_t* scratch, const RecoverSync& sync, hipStream_t st, Marks* marks) {
-  RecConsts rc;
-  rc.P2 = cs.P[1];
-  rc.p1 = cs.P[0].p;
-  rc.r_tilde = cs.r_tilde;
-  rc.k = pl.k;
-  rc.B = 1;
-  for (int i = 0; i < pl.k; ++i) rc.B *= 10;
-  rc.sh = __builtin_clzll(rc.B);
-  rc.d = rc.B << rc.sh;
-  rc.v = (uint64_t)((~(u128)0) / rc.d - ((u128)1 << 64));
-  rc.kinv = (uint32_t)(((1u << 22) + pl.k - 1) / pl.k);
-  rc.NP = pl.n + pl.m;
-  rc.nout = pl.na + pl.nb;
-  rc.nblk = (uint32_t)recover_blocks(pl);
-  rc.epoch = sync.epoch;
-  uint64_t* s = scratch;
-  uint32_t* cins = (uint32_t*)(scratch + rc.NP);
-  hipLaunchKernelGGL(k_rec_crt<kRecPT>, dim3(rc.nblk), dim3(kRecThreads + 1), 0, st, rc, res1, res2, s,
-                     sync.maps, cins, sync.counter, sync.status);
+hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, const DivTable* dt,
+                          hipStream_t st, Marks* marks) {
+  RecTable rt;
+  rt.P2 = cs.P[1];
+  rt.p1 = cs.P[0].p;
+  rt.r_tilde = cs.r_tilde;
+  for (int i = 0; i < 6; ++i) {
+    const int k = kMinK + i;
+    uint64_t B = 1;
+    for (int j = 0; j < k; ++j) B *= 10;
+    rt.B[i] = B;
+    rt.sh[i] = (uint32_t)__builtin_clzll(B);
+    rt.d[i] = B << rt.sh[i];
+    rt.v[i] = (uint64_t)((~(u128)0) / rt.d[i] - ((u128)1 << 64));
+    rt.kinv[i] = (uint32_t)(((1u << 22) + k - 1) / k);
+  }
+  hipLaunchKernelGGL(k_rec_crt<kRecPT>, dim3(sh.max_nblk, 1, w.count), dim3(kRecThreads + 1), 0, st, w, rt);
   if (marks) marks->mark(kRecCrt, st);
-  hipLaunchKernelGGL(k_rec_apply<kRecPT>, dim3(rc.nblk), dim3(kRecThreads), 0, st, rc, dt, s, cins, out);
+  hipLaunchKernelGGL(k_rec_apply<kRecPT>, dim3(sh.max_nblk, 1, w.count), dim3(kRecThreads), 0, st, w, rt, dt);
   if (marks) marks->mark(kRecApply, st);
   return hipGetLastError();
 }

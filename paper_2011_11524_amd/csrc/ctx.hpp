@@ -10,6 +10,11 @@
 
 namespace dmi {
 class BatchEngine;
+// Launch parameters per transform length log2 N, from the size-class tuner
+// (a text table: "log2N row_iters" per line), or defaults.
+struct TuneTable {
+  int row_iters[kMaxLogN + 1] = {};
+};
 struct PassTables {
   uint64_t* dev = nullptr;   // per prime: hi_fwd[R] lo_fwd[C] hi_inv[R] lo_inv[C]
 };
@@ -47,13 +52,18 @@ struct Profiler : Marks {
     spans.push_back({phase, last, i});
     last = i;
   }
+  // (phase, end time in ms since the first event) of every kernel of the
+  // work completed by the last dmul_sync
+  std::vector<std::pair<int, double>> timeline;
   void collect() {
+    timeline.clear();
     for (const Span& s : spans) {
-      float ms = 0.f;
+      float ms = 0.f, t = 0.f;
       if (hipEventElapsedTime(&ms, pool[s.a], pool[s.b]) == hipSuccess) {
         total_ms[s.phase] += ms;
         count[s.phase] += 1;
       }
+      if (hipEventElapsedTime(&t, pool[0], pool[s.b]) == hipSuccess) timeline.push_back({s.phase, t});
     }
     spans.clear();
     used = 0;
@@ -84,9 +94,9 @@ struct dmul_ctx {
   size_t batch_count = 0;
   dmi::BatchEngine* batch = nullptr;
   dmi::Profiler* prof = nullptr;
-  uint32_t* rec_sync = nullptr;         // recovery: [0] counter, [1..] map words
+  uint32_t* rec_sync = nullptr;         // recovery: [0] counter, [1..] map words (kept zero)
   size_t rec_sync_cap = 0;
-  uint32_t rec_epoch = 0;
+  dmi::TuneTable tune;                  // per transform length launch parameters
   std::mutex mu;
 };
 
@@ -95,7 +105,9 @@ int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl);
 size_t workspace_words(const PlanDev& pl);
 int get_twiddles(dmul_ctx* ctx, int logN, int logR, TwiddleSet* tw);
 int ensure_workspace(dmul_ctx* ctx, size_t words);
-int recover_sync(dmul_ctx* ctx, size_t nblk, int* status, RecoverSync* rs);
+int ensure_rec_sync(dmul_ctx* ctx, size_t words);
+int row_iters_for(const dmul_ctx* ctx, int logN);
+int from_hip(hipError_t e);
 int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
                     uint64_t* out, unsigned flags, int* status, uint64_t* residues);
 }  // namespace dmi

@@ -62,29 +62,43 @@ struct Marks {
   virtual ~Marks() = default;
 };
 
+// One product as the kernels see it.
+struct ProdDesc {
+  PlanDev pl;
+  const uint64_t* a;        // operands (device)
+  const uint64_t* b;
+  uint64_t* out;            // na + nb result limbs
+  uint64_t* ws;             // 4N words: X1 X2 Y1 Y2 (recovery scratch reuses Y)
+  int* status;              // bit 1: a limb >= 10^19; bit 2: a device-side wait gave up
+  uint32_t* rec_sync;       // [0] counter, [1..nblk] map words; zero between launches
+  uint32_t nblk;            // recovery workgroups
+  int square;               // a == b: one operand transformed
+};
+
+// A launch over products of one transform length: `one` when many is null,
+// else many[0 .. count) (device memory), one per blockIdx.z.
+struct Work {
+  ProdDesc one;
+  const ProdDesc* many;
+  uint32_t count;
+};
+
+// Grid shape shared by the products of a launch.
+struct Shape {
+  int logR, logC;
+  int any_nonsquare;        // some product transforms two operands
+  int row_iters;            // row groups per workgroup in the row pass
+  uint32_t max_nblk;        // largest recovery grid among the products
+};
+
 // Launch wrappers (ntt.hip, carry.hip).  All enqueue on `stream` and return
 // hipSuccess or the launch error.
-hipError_t launch_forward(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
-                          const DivTable* dt, const uint64_t* a, const uint64_t* b, bool square,
-                          uint64_t* bufs /* 4*N words: X1 X2 Y1 Y2 */,
-                          int* status, hipStream_t stream, Marks* marks);
-hipError_t launch_inverse(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
-                          uint64_t* bufs, bool square, hipStream_t stream, Marks* marks);
-// Answer recovery: `scratch` holds recover_scratch_words() words (s_i, then
-// per-workgroup carries).  The map words live in a buffer only the
-// recovery kernel writes, tagged with a per-launch epoch (24 bits, never
-// 0); `counter` is zero between launches; `status` receives bit 2 if a wait
-// for a map word gave up.
-struct RecoverSync {
-  uint32_t* maps;
-  uint32_t* counter;
-  int* status;
-  uint32_t epoch;
-};
-constexpr uint32_t kMaxEpoch = (1u << 24) - 1;
-hipError_t launch_recover(const PlanDev& pl, const Consts& cs, const DivTable* dt,
-                          const uint64_t* res1, const uint64_t* res2, uint64_t* out,
-                          uint64_t* scratch, const RecoverSync& sync, hipStream_t stream, Marks* marks);
+hipError_t launch_forward(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                          const DivTable* dt, hipStream_t stream, Marks* marks);
+hipError_t launch_inverse(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                          hipStream_t stream, Marks* marks);
+hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, const DivTable* dt,
+                          hipStream_t stream, Marks* marks);
 size_t recover_blocks(const PlanDev& pl);
 size_t recover_scratch_words(const PlanDev& pl);
 hipError_t launch_zero(uint64_t* out, size_t n, hipStream_t stream);

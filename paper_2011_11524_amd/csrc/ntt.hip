@@ -25,8 +25,6 @@
 // together with N^-1, by the scale R^2 N^-1 folded into the inverse
 // inter-pass table (the linearity trick, Section 6, merged with the
 // twiddle as Section 7.9 suggests).
-#include <stdlib.h>
-
 #include "internal.hpp"
 
 namespace dmi {
@@ -212,29 +210,39 @@ __device__ __forceinline__ uint64_t pass_factor(const uint64_t* __restrict__ hi,
   return mont_mul(hi[e >> logC], lo[e & C1], P);
 }
 
+// The product a kernel works on: the launch's single descriptor, or entry
+// blockIdx.z of the launch's descriptor array (a batch of products that
+// share one transform length).
+__device__ __forceinline__ ProdDesc load_desc(const Work& w) {
+  return w.many ? w.many[blockIdx.z] : w.one;
+}
+
 // ---------------------------------------------------------------------------
 // Pass A, forward: split + column DIF + inter-pass factor.
-// grid.x = C / T column tiles, grid.y = operand.  The digit groups of the
-// tile are split once, kept in registers, and transformed for each prime in
-// turn (the groups are below 10^k < p, the same residues for both primes).
-// The root tables of length R for both primes are staged in LDS.
+// grid.x = C / T column tiles, grid.y = operand, grid.z = product.  The
+// digit groups of the tile are split once, kept in registers, and
+// transformed for each prime in turn (the groups are below 10^k < p, the
+// same residues for both primes).  The root tables of length R for both
+// primes and the power-of-ten table are staged in LDS.
 // ---------------------------------------------------------------------------
 template <int LOGR, int LOGE, int T>
 __global__ void __launch_bounds__((T * Geometry<LOGR, LOGE>::NT))
-k_fwd_cols(PlanDev pl, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g,
-           const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
-           uint64_t* __restrict__ bufs, int* status) {
+k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) {
   using G = Geometry<LOGR, LOGE>;
   constexpr int R = G::L;
   constexpr int NTH = T * G::NT;                 // threads
   constexpr int PER = (R * T + NTH - 1) / NTH;   // tile points per thread
   extern __shared__ uint64_t lds[];
   uint64_t* troots = lds + T * G::STRIDE;        // [prime][R/2]
+  const ProdDesc d = load_desc(w);
   const int op = blockIdx.y;
-  const uint64_t* src = op ? b : a;
-  const uint64_t nl = op ? pl.nb : pl.na;
-  const uint64_t ng = op ? pl.m : pl.n;
-  const uint64_t C = (uint64_t)1 << pl.logC;
+  if (op == 1 && d.square) return;               // a square transforms one operand
+  const uint64_t* src = op ? d.b : d.a;
+  const uint64_t nl = op ? d.pl.nb : d.pl.na;
+  const uint64_t ng = op ? d.pl.m : d.pl.n;
+  const uint64_t N = d.pl.N;
+  const int logC = d.pl.logC;
+  const uint64_t C = (uint64_t)1 << logC;
   const uint64_t j0 = (uint64_t)blockIdx.x * T;
   __shared__ DivTable sdt;
   for (unsigned i = threadIdx.x; i < sizeof(DivTable) / 4; i += blockDim.x)
@@ -249,7 +257,7 @@ k_fwd_cols(PlanDev pl, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt
   for (int q = threadIdx.x; q < R * T; q += NTH) {
     const int row = q / T, col = q % T;
     lds[col * G::STRIDE + lds_pos<LOGE>(row)] =
-        j0 + col < C ? split_group(src, nl, ng, (uint64_t)row * C + j0 + col, pl.k, dt, status) : 0;
+        j0 + col < C ? split_group(src, nl, ng, (uint64_t)row * C + j0 + col, d.pl.k, dt, d.status) : 0;
   }
   __syncthreads();
   uint64_t v[PER];   // the split tile, kept for the second prime
@@ -262,7 +270,7 @@ k_fwd_cols(PlanDev pl, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt
 #pragma unroll 1
   for (int pi = 0; pi < 2; ++pi) {
     const Prime P = cs.P[pi];
-    uint64_t* dst = bufs + (size_t)(2 * op + pi) * pl.N;
+    uint64_t* dst = d.ws + (size_t)(2 * op + pi) * N;
     if (pi == 1) {
 #pragma unroll
       for (int s = 0; s < PER; ++s) {
@@ -277,7 +285,7 @@ k_fwd_cols(PlanDev pl, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt
       if (j0 + c >= C) continue;
       const uint64_t e = (uint64_t)bitrev(row, LOGR) * (j0 + c);
       uint64_t x = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
-      x = mont_mul(x, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], e, pl.logC, P), P);
+      x = mont_mul(x, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], e, logC, P), P);
       dst[(uint64_t)row * C + j0 + c] = x;
     }
     __syncthreads();
@@ -289,9 +297,9 @@ k_fwd_cols(PlanDev pl, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt
 // (operand, prime) buffer.  Inverse: pointwise REDC(X, Y) then DIT, written
 // over X.
 //
-// grid.y selects the buffer (forward: prime + 2*operand; inverse: prime);
-// the workgroups along x loop over groups of RPW rows of that buffer.  A
-// thread holds points t + j*NT of its row (j < E): that
+// grid.y selects the buffer (forward: prime + 2*operand; inverse: prime),
+// grid.z the product; the workgroups along x loop over groups of RPW rows
+// of that buffer.  A thread holds points t + j*NT of its row (j < E): that
 // is the coalesced layout of the global loads, the first DIF round (top
 // bits) runs on it without an LDS round trip, and the last DIT round ends
 // in it and is stored straight to global memory.  With TWL the row
@@ -299,17 +307,19 @@ k_fwd_cols(PlanDev pl, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt
 // ---------------------------------------------------------------------------
 template <int LOGC, int LOGE, int RPW, bool INV, bool TWL>
 __global__ void __launch_bounds__((RPW * Geometry<LOGC, LOGE>::NT))
-k_rows(PlanDev pl, Consts cs, TwiddleSet tw, uint64_t* __restrict__ bufs, int square) {
+k_rows(Work w, Consts cs, TwiddleSet tw) {
   using G = Geometry<LOGC, LOGE>;
   constexpr int C = G::L, E = G::E, NT = G::NT;
   constexpr int NR = G::ROUNDS;
   extern __shared__ uint64_t lds[];
+  const ProdDesc d = load_desc(w);
   const int y = blockIdx.y;
+  if (!INV && y >= 2 && d.square) return;
   const int pi = y & 1;
   const Prime P = cs.P[pi];
-  uint64_t* X = bufs + (size_t)y * pl.N;                       // inverse: y = prime
-  const uint64_t* Y = bufs + (size_t)(square ? pi : 2 + pi) * pl.N;
-  const uint64_t R = (uint64_t)1 << pl.logR;
+  uint64_t* X = d.ws + (size_t)y * d.pl.N;                       // inverse: y = prime
+  const uint64_t* Y = d.ws + (size_t)(d.square ? pi : 2 + pi) * d.pl.N;
+  const uint64_t R = (uint64_t)1 << d.pl.logR;
   const uint32_t groups = (uint32_t)((R + RPW - 1) / RPW);
   const int r = threadIdx.x / NT, t = threadIdx.x % NT;
   uint64_t* row_lds = lds + r * G::STRIDE;
@@ -320,10 +330,10 @@ k_rows(PlanDev pl, Consts cs, TwiddleSet tw, uint64_t* __restrict__ bufs, int sq
     uint64_t* tl = lds + RPW * G::STRIDE;
     for (int i = threadIdx.x; i < C / 2; i += blockDim.x) tl[i] = roots_g[i];
     roots = tl;
+    __syncthreads();
   }
 
   uint64_t cur[E];
-  if constexpr (TWL) __syncthreads();
   for (uint32_t g = blockIdx.x; g < groups; g += gridDim.x) {
     const uint64_t row = (uint64_t)g * RPW + r;
     if (row < R) {
@@ -371,17 +381,20 @@ k_rows(PlanDev pl, Consts cs, TwiddleSet tw, uint64_t* __restrict__ bufs, int sq
 // ---------------------------------------------------------------------------
 // Pass A, inverse: inter-pass factor with scale, then column DIT; the
 // result is the residue of each convolution coefficient, in natural order.
+// grid.x = column tiles, grid.y = prime, grid.z = product.
 // ---------------------------------------------------------------------------
 template <int LOGR, int LOGE, int T>
 __global__ void __launch_bounds__((T * Geometry<LOGR, LOGE>::NT))
-k_inv_cols(PlanDev pl, Consts cs, TwiddleSet tw, uint64_t* __restrict__ bufs) {
+k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   using G = Geometry<LOGR, LOGE>;
   extern __shared__ uint64_t lds[];
   uint64_t* troots = lds + T * G::STRIDE;
+  const ProdDesc d = load_desc(w);
   const int pi = blockIdx.y;
   const Prime P = cs.P[pi];
-  uint64_t* X = bufs + (size_t)pi * pl.N;
-  const uint64_t C = (uint64_t)1 << pl.logC;
+  uint64_t* X = d.ws + (size_t)pi * d.pl.N;
+  const int logC = d.pl.logC;
+  const uint64_t C = (uint64_t)1 << logC;
   const uint64_t j0 = (uint64_t)blockIdx.x * T;
   constexpr int R = G::L;
 
@@ -393,7 +406,7 @@ k_inv_cols(PlanDev pl, Consts cs, TwiddleSet tw, uint64_t* __restrict__ bufs) {
     if (j0 + c < C) {
       const uint64_t e = (uint64_t)bitrev(row, LOGR) * (j0 + c);
       v = X[(uint64_t)row * C + j0 + c];
-      v = mont_mul(v, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], e, pl.logC, P), P);
+      v = mont_mul(v, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], e, logC, P), P);
     }
     lds[c * G::STRIDE + lds_pos<LOGE>(row)] = v;
   }
@@ -433,94 +446,74 @@ static hipError_t prepare(K kernel, size_t lds_bytes) {
 }
 
 template <int LOGR>
-static hipError_t fwd_cols_l(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
-                             const DivTable* dt, const uint64_t* a, const uint64_t* b, bool square,
-                             uint64_t* bufs, int* status, hipStream_t st) {
+static hipError_t fwd_cols_l(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                             const DivTable* dt, hipStream_t st) {
   constexpr int LOGE = loge_for(LOGR), T = fwd_cols_per_tile(LOGR);
   using G = Geometry<LOGR, LOGE>;
   const size_t lds = ((size_t)T * G::STRIDE + (size_t)G::L) * sizeof(uint64_t);
   auto kern = k_fwd_cols<LOGR, LOGE, T>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
-  const uint64_t C = (uint64_t)1 << pl.logC;
-  dim3 grid((unsigned)((C + T - 1) / T), square ? 1 : 2);
-  hipLaunchKernelGGL(kern, grid, dim3(T * G::NT), lds, st, pl, cs, tw, dt, a, b, bufs, status);
+  const uint64_t C = (uint64_t)1 << sh.logC;
+  dim3 grid((unsigned)((C + T - 1) / T), sh.any_nonsquare ? 2 : 1, w.count);
+  hipLaunchKernelGGL(kern, grid, dim3(T * G::NT), lds, st, w, cs, tw, dt);
   return hipGetLastError();
 }
 
-// Tuning knobs of the row pass (read once from the environment, for
-// experiments): DMUL_ROWS_TWL=1 stages root tables in LDS, DMUL_ROWS_ITERS
-// is the number of row groups each workgroup loops over.
-struct RowTuning {
-  int twl = 1;
-  int iters = 1;
-};
-static RowTuning row_tuning() {
-  static RowTuning rt = [] {
-    RowTuning t;
-    if (const char* e = getenv("DMUL_ROWS_TWL")) t.twl = atoi(e);
-    if (const char* e = getenv("DMUL_ROWS_ITERS")) t.iters = atoi(e) > 0 ? atoi(e) : 1;
-    return t;
-  }();
-  return rt;
-}
-
 template <int LOGC, bool INV, bool TWL>
-static hipError_t rows_launch(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
-                              uint64_t* bufs, bool square, hipStream_t st) {
+static hipError_t rows_launch(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                              hipStream_t st) {
   constexpr int LOGE = loge_for(LOGC), RPW = rows_per_wg(LOGC);
   using G = Geometry<LOGC, LOGE>;
   const size_t lds = ((size_t)RPW * G::STRIDE + (TWL ? (size_t)G::L / 2 : 0)) * sizeof(uint64_t);
   auto kern = k_rows<LOGC, LOGE, RPW, INV, TWL>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
-  const uint64_t R = (uint64_t)1 << pl.logR;
+  const uint64_t R = (uint64_t)1 << sh.logR;
   const uint64_t groups = (R + RPW - 1) / RPW;
-  const int iters = row_tuning().iters;
+  const int iters = sh.row_iters > 0 ? sh.row_iters : 1;
   const unsigned gx = (unsigned)((groups + iters - 1) / iters);
-  const unsigned ny = INV ? 2 : (square ? 2 : 4);
-  hipLaunchKernelGGL(kern, dim3(gx, ny), dim3(RPW * G::NT), lds, st, pl, cs, tw, bufs, square ? 1 : 0);
+  const unsigned ny = INV ? 2 : (sh.any_nonsquare ? 4 : 2);
+  hipLaunchKernelGGL(kern, dim3(gx, ny, w.count), dim3(RPW * G::NT), lds, st, w, cs, tw);
   return hipGetLastError();
 }
 
 template <int LOGC, bool INV>
-static hipError_t rows_l(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw, uint64_t* bufs,
-                         bool square, hipStream_t st) {
-  if (row_tuning().twl) return rows_launch<LOGC, INV, true>(pl, cs, tw, bufs, square, st);
-  return rows_launch<LOGC, INV, false>(pl, cs, tw, bufs, square, st);
+static hipError_t rows_l(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                         hipStream_t st) {
+  return rows_launch<LOGC, INV, true>(w, sh, cs, tw, st);
 }
 
 template <int LOGR>
-static hipError_t inv_cols_l(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
-                             uint64_t* bufs, hipStream_t st) {
+static hipError_t inv_cols_l(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                             hipStream_t st) {
   constexpr int LOGE = loge_for(LOGR), T = cols_per_tile(LOGR);
   using G = Geometry<LOGR, LOGE>;
   const size_t lds = ((size_t)T * G::STRIDE + (size_t)G::L / 2) * sizeof(uint64_t);
   auto kern = k_inv_cols<LOGR, LOGE, T>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
-  const uint64_t C = (uint64_t)1 << pl.logC;
-  dim3 grid((unsigned)((C + T - 1) / T), 2);
-  hipLaunchKernelGGL(kern, grid, dim3(T * G::NT), lds, st, pl, cs, tw, bufs);
+  const uint64_t C = (uint64_t)1 << sh.logC;
+  dim3 grid((unsigned)((C + T - 1) / T), 2, w.count);
+  hipLaunchKernelGGL(kern, grid, dim3(T * G::NT), lds, st, w, cs, tw);
   return hipGetLastError();
 }
 
 #define DMUL_LEN_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13)
 
-hipError_t launch_forward(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
-                          const DivTable* dt, const uint64_t* a, const uint64_t* b, bool square,
-                          uint64_t* bufs, int* status, hipStream_t st, Marks* marks) {
+hipError_t launch_forward(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                          const DivTable* dt, hipStream_t st, Marks* marks) {
   hipError_t e = hipErrorInvalidValue;
-  switch (pl.logR) {
-#define X(l) case l: e = fwd_cols_l<l>(pl, cs, tw, dt, a, b, square, bufs, status, st); break;
+  switch (sh.logR) {
+#define X(l) case l: e = fwd_cols_l<l>(w, sh, cs, tw, dt, st); break;
     DMUL_LEN_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
   if (marks) marks->mark(kFwdCols, st);
-  switch (pl.logC) {
-#define X(l) case l: e = rows_l<l, false>(pl, cs, tw, bufs, square, st); break;
+  switch (sh.logC) {
+#define X(l) case l: e = rows_l<l, false>(w, sh, cs, tw, st); break;
     DMUL_LEN_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;
@@ -529,19 +522,19 @@ hipError_t launch_forward(const PlanDev& pl, const Consts& cs, const TwiddleSet&
   return e;
 }
 
-hipError_t launch_inverse(const PlanDev& pl, const Consts& cs, const TwiddleSet& tw,
-                          uint64_t* bufs, bool square, hipStream_t st, Marks* marks) {
+hipError_t launch_inverse(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                          hipStream_t st, Marks* marks) {
   hipError_t e = hipErrorInvalidValue;
-  switch (pl.logC) {
-#define X(l) case l: e = rows_l<l, true>(pl, cs, tw, bufs, square, st); break;
+  switch (sh.logC) {
+#define X(l) case l: e = rows_l<l, true>(w, sh, cs, tw, st); break;
     DMUL_LEN_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
   if (marks) marks->mark(kInvRows, st);
-  switch (pl.logR) {
-#define X(l) case l: e = inv_cols_l<l>(pl, cs, tw, bufs, st); break;
+  switch (sh.logR) {
+#define X(l) case l: e = inv_cols_l<l>(w, sh, cs, tw, st); break;
     DMUL_LEN_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;

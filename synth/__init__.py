@@ -129,7 +129,7 @@ class OperandPool:
         x = self.limbs[off: off + nl].copy()
         top_digits = d - (nl - 1) * LIMB_DIGITS
         lo = 10 ** (top_digits - 1)
-        x[-1] = np.uint64(int(self.rng.integers(lo, 10 * lo)))
+        x[-1] = self.rng.integers(lo, 10 * lo, dtype=np.uint64)
         return x
 
 
