@@ -177,6 +177,55 @@ def run_batched(dm, ctx, torch, steps: int, warmup: int, count: int):
     return res
 
 
+def run_serving(dm, torch, count: int, seed: int = 5005):
+    """The serving workload: `count` requests, each operand length
+    round(10^U(2, 7)) digits, Poisson arrivals at 70% of the device's service
+    rate (measured on a calibration draw served back to back), operands
+    resident in HBM as slices of one random pool; continuous batching over
+    two engines.  A seeded sample of requests is re-run alone and compared."""
+    import numpy as np
+    import synth
+    from paper_2011_11524_amd import serve
+    pool_limbs = 1 << 21
+    pool_h = synth.pack_digits(np.random.default_rng(seed + 10).integers(0, 10, size=pool_limbs * 19,
+                                                                          dtype=np.uint8))
+    pool = dm.to_device(pool_h)
+    budget = 8 << 30
+    srv = serve.Server(pool, engines=2, budget_bytes=budget, max_batch=2048)
+    try:
+        ncal = min(2000, count)
+        la, lb = synth.serving_lengths(ncal, seed=seed + 1)
+        cal = serve.make_requests(la, lb, np.zeros(ncal), pool_limbs, seed=seed + 2)
+        srv.run(cal, realtime=False)                       # warm-up: tables, workspaces
+        st_cal, _ = srv.run(cal, realtime=False)
+        service = st_cal.wall_s / ncal                     # seconds per request, back to back
+        rate = 0.7 / service
+        la, lb = synth.serving_lengths(count, seed=seed)
+        arr = synth.poisson_arrivals(count, rate, seed=seed + 3)
+        reqs = serve.make_requests(la, lb, arr, pool_limbs, seed=seed + 4)
+        rng = np.random.default_rng(seed + 5)
+        check = set(int(i) for i in rng.choice(count, size=min(200, count), replace=False))
+        stats, _ = srv.run(reqs, realtime=True)
+        # alone vs in the mix, on a sample: serve the sample again as part of
+        # a mix (all at once) and alone, and compare
+        sample = [reqs[i] for i in sorted(check)]
+        _, mixed = srv.run([serve.Request(k, r.a_off, r.na, r.b_off, r.nb, 0.0)
+                            for k, r in enumerate(sample)], keep_outputs=True, realtime=False)
+    finally:
+        srv.close()
+    ctx = dm.Context(0)
+    same = True
+    for k, r in enumerate(sample):
+        alone = ctx.mul(pool[r.a_off: r.a_off + r.na].contiguous(), pool[r.b_off: r.b_off + r.nb].contiguous())
+        same = same and torch.equal(alone, mixed[k])
+    ctx.close()
+    out = stats.summary()
+    out.update({"service_us_per_request": service * 1e6, "arrival_rate_per_s": rate,
+                "target_load": 0.7, "alone_vs_mix_sample": len(sample),
+                "alone_vs_mix": "identical" if same else "DIFFERENT"})
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +236,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched", action="store_true", help="also run the batched workload")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--serving", action="store_true", help="also run the serving workload")
+    ap.add_argument("--requests", type=int, default=100_000)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size (counter calibration)")
     args = ap.parse_args()
@@ -291,6 +342,9 @@ def main() -> int:
     if args.batched:
         result["batched"] = run_batched(dm, ctx, torch, max(2, args.steps // 5), 1, args.batch_count)
         print(f"[bench] batched: {json.dumps(result['batched'])}", flush=True)
+    if args.serving:
+        result["serving"] = run_serving(dm, torch, args.requests)
+        print(f"[bench] serving: {json.dumps(result['serving'])}", flush=True)
 
     if not args.no_cpu_baseline:
         want, times = cpu_baseline(a, b, args.cpu_budget, 3)

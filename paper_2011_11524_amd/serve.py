@@ -1,0 +1,213 @@
+"""Serving loop: continuous batching of multiplication requests.
+
+Requests arrive over time (each names its two operands as slices of a pool
+of limbs resident in HBM).  The loop admits waiting requests in arrival
+order while their device footprint -- the product's workspace
+(dmul_workspace_bytes) plus its na + nb result limbs -- fits the budget of a
+free engine, and launches the admitted set as one dmul_batch on that
+engine's stream.  With two or more engines (each a dmul context with its own
+HIP stream and workspace), a new batch is formed and launched while earlier
+ones still run, so requests that arrive during a batch join the next one
+instead of waiting for the device to drain: continuous batching, with the
+work of successive batches overlapping on the device.
+
+Each request's latency is the time from its arrival to the host observing
+its batch complete (a HIP event on the engine's stream).  The loop is
+argument marshalling and bookkeeping only; every product runs in the
+library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import Context, DmulError, lib, torch, workspace_bytes
+
+
+@dataclass
+class Request:
+    rid: int
+    a_off: int          # limb offset of operand a in the pool
+    na: int             # limbs of a
+    b_off: int
+    nb: int
+    arrival: float      # seconds after the start of the run
+
+
+@dataclass
+class ServeStats:
+    completed: int = 0
+    digits: int = 0
+    wall_s: float = 0.0
+    batches: int = 0
+    latencies_s: list = field(default_factory=list)
+    max_inflight_bytes: int = 0
+    max_overlap: int = 0        # largest number of batches in flight at once
+
+    def summary(self) -> dict:
+        lat = np.asarray(self.latencies_s, dtype=float) * 1e3
+        return {
+            "requests": self.completed,
+            "batches": self.batches,
+            "digits": self.digits,
+            "wall_s": self.wall_s,
+            "digits_per_s": self.digits / self.wall_s if self.wall_s > 0 else None,
+            "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+            "mean_batch": self.completed / self.batches if self.batches else 0,
+            "max_inflight_bytes": self.max_inflight_bytes,
+            "max_batches_in_flight": self.max_overlap,
+        }
+
+
+class _Engine:
+    """One dmul context with its own stream; at most one batch in flight."""
+
+    def __init__(self, device: int, budget: int):
+        self.stream = torch.cuda.Stream(device=device)
+        self.ctx = Context(device, budget_bytes=0, stream=self.stream)
+        self.budget = budget
+        self.busy = None            # (event, requests, out buffer, bytes) of the batch in flight
+
+    def close(self):
+        self.ctx.close()
+
+
+class Server:
+    """Continuous-batching server over a resident operand pool.
+
+    pool: 1-D torch.uint64 CUDA tensor of limbs; requests reference slices.
+    engines: number of contexts/streams (>= 2 lets batches overlap).
+    budget_bytes: device footprint one engine may hold in flight.
+    max_batch: most requests per batch.
+    """
+
+    def __init__(self, pool, device: int = 0, engines: int = 2, budget_bytes: int = 8 << 30,
+                 max_batch: int = 1024):
+        self.pool = pool
+        self.device = device
+        self.engines = [_Engine(device, budget_bytes) for _ in range(max(1, engines))]
+        self.max_batch = max_batch
+        self._base = pool.data_ptr()
+        lib()
+
+    def close(self):
+        for e in self.engines:
+            e.close()
+
+    @staticmethod
+    def footprint(na: int, nb: int) -> int:
+        return workspace_bytes(na, nb) + 8 * (na + nb)
+
+    def _launch(self, eng: _Engine, reqs: list, keep_outputs: bool):
+        """Enqueue one batch: output buffer, dmul_batch, completion event."""
+        total = sum(r.na + r.nb for r in reqs)
+        with torch.cuda.stream(eng.stream):
+            out = torch.empty(total, dtype=torch.uint64, device=f"cuda:{self.device}")
+        n = len(reqs)
+        A = (ctypes.c_void_p * n)()
+        B = (ctypes.c_void_p * n)()
+        O = (ctypes.c_void_p * n)()
+        NA = (ctypes.c_size_t * n)()
+        NB = (ctypes.c_size_t * n)()
+        st = (ctypes.c_int32 * n)()
+        base, optr, ofs = self._base, out.data_ptr(), 0
+        for i, r in enumerate(reqs):
+            A[i] = base + 8 * r.a_off
+            B[i] = base + 8 * r.b_off
+            NA[i] = r.na
+            NB[i] = r.nb
+            O[i] = optr + 8 * ofs
+            ofs += r.na + r.nb
+        rc = eng.ctx._lib.dmul_batch(eng.ctx._h, n, A, NA, B, NB, O, st, 0)
+        if rc:
+            raise DmulError(rc, "dmul_batch")
+        ev = torch.cuda.Event()
+        ev.record(eng.stream)
+        nbytes = sum(self.footprint(r.na, r.nb) for r in reqs)
+        eng.busy = (ev, reqs, out if keep_outputs else None, nbytes, (A, B, O, NA, NB, st))
+
+    def _retire(self, eng: _Engine, t0: float, stats: ServeStats, results: dict | None):
+        ev, reqs, out, nbytes, keep = eng.busy
+        now = time.perf_counter() - t0
+        rc = eng.ctx._lib.dmul_sync(eng.ctx._h)      # stream already idle: returns at once
+        if rc:
+            raise DmulError(rc, "dmul_sync")
+        st = keep[5]
+        for i, r in enumerate(reqs):
+            if st[i] != 0:
+                raise DmulError(st[i], f"request {r.rid}")
+            stats.latencies_s.append(now - r.arrival)
+            stats.digits += 19 * (r.na + r.nb)
+        stats.completed += len(reqs)
+        if results is not None and out is not None:
+            ofs = 0
+            for r in reqs:
+                results[r.rid] = out[ofs: ofs + r.na + r.nb]
+                ofs += r.na + r.nb
+        eng.busy = None
+
+    def run(self, reqs: list, keep_outputs: bool = False, realtime: bool = True) -> tuple[ServeStats, dict]:
+        """Serve `reqs` (sorted by arrival).  With realtime, a request is
+        admitted only once its arrival time has passed; otherwise all are
+        available at once.  Returns the statistics and, with keep_outputs,
+        {rid: result tensor}."""
+        stats = ServeStats()
+        results = {} if keep_outputs else None
+        nxt = 0                      # next request not yet admitted
+        t0 = time.perf_counter()
+        while stats.completed < len(reqs):
+            now = time.perf_counter() - t0
+            for eng in self.engines:
+                if eng.busy is not None and eng.busy[0].query():
+                    self._retire(eng, t0, stats, results)
+            inflight = sum(1 for e in self.engines if e.busy is not None)
+            launched = False
+            for eng in self.engines:
+                if eng.busy is not None or nxt >= len(reqs):
+                    continue
+                if realtime and reqs[nxt].arrival > now:
+                    break
+                batch, used = [], 0
+                while (nxt < len(reqs) and len(batch) < self.max_batch
+                       and (not realtime or reqs[nxt].arrival <= now)):
+                    r = reqs[nxt]
+                    fp = self.footprint(r.na, r.nb)
+                    if batch and used + fp > eng.budget:
+                        break
+                    batch.append(r)
+                    used += fp
+                    nxt += 1
+                self._launch(eng, batch, keep_outputs)
+                stats.batches += 1
+                inflight += 1
+                stats.max_overlap = max(stats.max_overlap, inflight)
+                stats.max_inflight_bytes = max(
+                    stats.max_inflight_bytes, sum(e.busy[3] for e in self.engines if e.busy is not None))
+                launched = True
+            if not launched:
+                if all(e.busy is None for e in self.engines) and nxt < len(reqs) and realtime:
+                    wait = reqs[nxt].arrival - (time.perf_counter() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 1e-3))
+                else:
+                    time.sleep(2e-5)
+        stats.wall_s = time.perf_counter() - t0
+        return stats, (results or {})
+
+
+def make_requests(lengths_a, lengths_b, arrivals, pool_limbs: int, seed: int = 5008) -> list:
+    """Requests whose operands are random slices of a pool of `pool_limbs`
+    limbs (digit lengths rounded up to whole limbs)."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i, (da, db, t) in enumerate(zip(lengths_a, lengths_b, arrivals)):
+        na = max(1, (int(da) + 18) // 19)
+        nb = max(1, (int(db) + 18) // 19)
+        ao = int(rng.integers(0, pool_limbs - na + 1))
+        bo = int(rng.integers(0, pool_limbs - nb + 1))
+        reqs.append(Request(i, ao, na, bo, nb, float(t)))
+    return reqs
