@@ -141,9 +141,16 @@ def run_batched(dm, ctx, torch, steps: int, warmup: int, count: int):
         ctx.sync()
         return st
 
+    def batched_graph():
+        st = gctx.batch_async(pairs, outs_b, graph=True)
+        gctx.sync()
+        return st
+
+    gctx = dm.Context(0, stream=torch.cuda.Stream())
+
     res = {"products": count, "digits": digits,
            "size_classes": {int(k): int(v) for k, v in zip(*np.unique(logn, return_counts=True))}}
-    for name, fn in (("per_product", one_by_one), ("batched", batched)):
+    for name, fn in (("per_product", one_by_one), ("batched", batched), ("batched_graph", batched_graph)):
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
@@ -167,7 +174,9 @@ def run_batched(dm, ctx, torch, steps: int, warmup: int, count: int):
     for name, lat in (("per_product", lat_pp), ("batched", lat_b)):
         res[name]["p50_ms"] = _pct(lat, 50)
         res[name]["p99_ms"] = _pct(lat, 99)
+    gctx.close()
     res["speedup"] = res["per_product"]["ms_per_batch"] / res["batched"]["ms_per_batch"]
+    res["speedup_graph"] = res["per_product"]["ms_per_batch"] / res["batched_graph"]["ms_per_batch"]
     # every batched result equals its per-product result; a sample against the oracle
     same = all(torch.equal(x, y) for x, y in zip(outs_a, outs_b))
     rng = np.random.default_rng(4007)

@@ -63,6 +63,13 @@ extern "C" {
  * not depend on k. */
 #define DMUL_FLAG_FORCE_K(k) ((unsigned)(k) & 0x1fu)
 #define DMUL_FLAG_K_MASK 0x1fu
+/* dmul_batch only: capture the batch's kernels in a HIP graph and replay
+ * that graph when an identical batch (same pointers, sizes and flags) is
+ * submitted again on the same context.  Needs a context stream set by
+ * dmul_ctx_set_stream (the legacy null stream cannot be captured); without
+ * one the flag is ignored.  Captured batches are dropped when the context's
+ * batch buffers grow (at most 8 are kept). */
+#define DMUL_FLAG_GRAPH 0x100u
 
 typedef struct dmul_ctx dmul_ctx;
 
@@ -161,6 +168,14 @@ int dmul_ctx_profile_read(dmul_ctx* ctx, double* total_ms, uint64_t* launches, i
  * kernels (fills at most n). */
 int dmul_ctx_profile_events(dmul_ctx* ctx, int32_t* phases, double* end_ms, int n);
 const char* dmul_phase_name(int phase);
+
+/* Size-class tuning: for products of transform length 2^log2_n, every
+ * workgroup of the row pass loops over `row_iters` groups of rows (0 = the
+ * default).  Contexts start from the table written by the project's
+ * autotuner (dmul_tune.txt beside the library, or the file named by
+ * DMUL_TUNE_TABLE: lines "log2_n row_iters").  Returns DMUL_OK or
+ * DMUL_EINVAL. */
+int dmul_ctx_tune(dmul_ctx* ctx, int log2_n, int row_iters);
 
 /* Library version string. */
 const char* dmul_version(void);

@@ -28,12 +28,13 @@ DMUL_EDIGIT = -2
 DMUL_ERANGE = -3
 DMUL_ENOMEM = -4
 DMUL_EDEVICE = -5
+DMUL_FLAG_GRAPH = 0x100
 
 # Every function the header declares (checked by the test suite).
 EXPORTS = ("dmul", "dmul_ctx_create", "dmul_ctx_destroy", "dmul_ctx_set_stream", "dmul_ex",
            "dmul_sync", "dmul_batch", "dmul_plan", "dmul_workspace_bytes", "dmul_strerror",
            "dmul_host", "dmul_primes", "dmul_debug_residues", "dmul_version", "dmul_ctx_profile",
-           "dmul_ctx_profile_read", "dmul_phase_name", "dmul_ctx_profile_events")
+           "dmul_ctx_profile_read", "dmul_phase_name", "dmul_ctx_profile_events", "dmul_ctx_tune")
 
 
 class DmulError(RuntimeError):
@@ -103,6 +104,7 @@ def lib():
                                         ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
     L.dmul_ctx_profile_events.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    L.dmul_ctx_tune.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.dmul_phase_name.argtypes = [ctypes.c_int]
     L.dmul_phase_name.restype = ctypes.c_char_p
     _lib = L
@@ -211,9 +213,10 @@ class Context:
         return out
 
     # -- batches -------------------------------------------------------------
-    def batch_async(self, pairs: Sequence, outs: Sequence, force_k: int = 0):
+    def batch_async(self, pairs: Sequence, outs: Sequence, force_k: int = 0, graph: bool = False):
         """Enqueue len(pairs) products (a_i, b_i) -> outs[i]; returns the host
-        status array that sync() fills in."""
+        status array that sync() fills in.  graph=True captures the batch in
+        a HIP graph, replayed when the same batch is submitted again."""
         n = len(pairs)
         A = (ctypes.c_void_p * n)()
         B = (ctypes.c_void_p * n)()
@@ -227,18 +230,25 @@ class Context:
             O[i] = o.data_ptr() if o.numel() else 0
             NA[i] = a.numel()
             NB[i] = b.numel()
-        rc = self._lib.dmul_batch(self._h, n, A, NA, B, NB, O, st, flags_for(force_k))
+        flags = flags_for(force_k) | (DMUL_FLAG_GRAPH if graph else 0)
+        rc = self._lib.dmul_batch(self._h, n, A, NA, B, NB, O, st, flags)
         if rc:
             raise DmulError(rc, "dmul_batch")
         self._keep = (A, B, O, NA, NB)
         return st
 
-    def batch(self, pairs: Sequence, force_k: int = 0):
-        outs = [torch.empty(a.numel() + b.numel(), dtype=torch.uint64, device=a.device)
-                for a, b in pairs]
-        st = self.batch_async(pairs, outs, force_k)
+    def batch(self, pairs: Sequence, force_k: int = 0, graph: bool = False, outs=None):
+        if outs is None:
+            outs = [torch.empty(a.numel() + b.numel(), dtype=torch.uint64, device=a.device)
+                    for a, b in pairs]
+        st = self.batch_async(pairs, outs, force_k, graph)
         self.sync()
         return outs, [int(s) for s in st]
+
+    def tune(self, log2_n: int, row_iters: int) -> None:
+        rc = self._lib.dmul_ctx_tune(self._h, int(log2_n), int(row_iters))
+        if rc:
+            raise DmulError(rc, "dmul_ctx_tune")
 
     # -- per-kernel timing ----------------------------------------------------
     def profile(self, enable: bool) -> None:

@@ -584,6 +584,14 @@ int dmul_debug_residues(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_
   return rc ? rc : rs;
 }
 
+int dmul_ctx_tune(dmul_ctx* c, int log2_n, int row_iters) {
+  if (!c || log2_n < 0 || log2_n > kMaxLogN || row_iters < 0 || row_iters > 64) return DMUL_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->tune.row_iters[log2_n] = row_iters;
+  if (c->batch) c->batch->forget_graphs();
+  return DMUL_OK;
+}
+
 int dmul_ctx_profile(dmul_ctx* c, int enable) {
   if (!c) return DMUL_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
@@ -629,7 +637,7 @@ int dmul_batch(dmul_ctx* c, size_t count, const uint64_t* const* a, const size_t
                const uint64_t* const* b, const size_t* nb, uint64_t* const* out,
                int32_t* status, unsigned flags) {
   if (!c || (count && (!a || !na || !b || !nb || !out || !status))) return DMUL_EINVAL;
-  if (flags & ~DMUL_FLAG_K_MASK) return DMUL_EINVAL;
+  if (flags & ~(DMUL_FLAG_K_MASK | DMUL_FLAG_GRAPH)) return DMUL_EINVAL;
   for (size_t i = 0; i < count; ++i) {
     const int rc = check_args(a[i], na[i], b[i], nb[i], out[i]);
     if (rc) return rc;

@@ -15,7 +15,16 @@
 
 namespace dmi {
 
+void BatchEngine::drop_graphs() {
+  for (auto& kv : graphs_) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.descs) (void)hipFree(kv.second.descs);
+  }
+  graphs_.clear();
+}
+
 BatchEngine::~BatchEngine() {
+  drop_graphs();
   if (ws_) (void)hipFree(ws_);
   if (sync_) (void)hipFree(sync_);
   if (d_desc_) (void)hipFree(d_desc_);
@@ -29,6 +38,7 @@ int BatchEngine::reserve(dmul_ctx* ctx, size_t ws_words, size_t sync_words, size
   if (ctx->budget && ws_words * sizeof(uint64_t) > ctx->budget) return DMUL_ENOMEM;
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return from_hip(e);
+  drop_graphs();   // captured batches point into the buffers being replaced
   if (ws_words > ws_words_) {
     if (ws_) (void)hipFree(ws_);
     ws_ = nullptr;
@@ -76,7 +86,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       if (e != hipSuccess) return from_hip(e);
       continue;
     }
-    const int rc = make_plan(na[i], nb[i], flags, &plans[i]);
+    const int rc = make_plan(na[i], nb[i], flags & DMUL_FLAG_K_MASK, &plans[i]);
     if (rc) {
       status[i] = rc;
       continue;
@@ -124,28 +134,87 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
     }
     cls.push_back(c);
   }
-  hipError_t e = hipMemcpyAsync(d_desc_, h_desc_, nvalid * sizeof(ProdDesc), hipMemcpyHostToDevice,
+  for (const Cls& c : cls) {                 // tables exist before any capture
+    TwiddleSet tw;
+    rc = get_twiddles(ctx, c.logN, c.sh.logR, &tw);
+    if (rc) return rc;
+  }
+  // hipGraph replay: a batch identical to a captured one (same operands,
+  // outputs, sizes, flags) relaunches the captured kernel sequence.  The
+  // legacy null stream cannot be captured, so graphs need a created stream.
+  const bool graph = (flags & DMUL_FLAG_GRAPH) && ctx->stream != nullptr && !ctx->prof;
+  uint64_t sig = 1469598103934665603ULL;
+  auto mix = [&sig](uint64_t v) { sig = (sig ^ v) * 1099511628211ULL; };
+  if (graph) {
+    mix(nvalid);
+    mix(flags);
+    for (size_t i = 0; i < nvalid; ++i) {
+      const ProdDesc& d = h_desc_[i];
+      mix((uint64_t)d.a); mix((uint64_t)d.b); mix((uint64_t)d.out); mix(d.pl.na); mix(d.pl.nb);
+      mix((uint64_t)d.status); mix((uint64_t)d.ws);
+    }
+    auto it = graphs_.find(sig);
+    if (it != graphs_.end()) {
+      if (hipEventRecord(copied_, ctx->stream) != hipSuccess) return DMUL_EDEVICE;
+      return from_hip(hipGraphLaunch(it->second.exec, ctx->stream));
+    }
+  }
+  ProdDesc* descs = d_desc_;
+  if (graph) {
+    if (graphs_.size() >= 8) drop_graphs();
+    hipError_t e = hipMalloc(&descs, nvalid * sizeof(ProdDesc));
+    if (e != hipSuccess) return from_hip(e);
+  }
+  hipError_t e = hipMemcpyAsync(descs, h_desc_, nvalid * sizeof(ProdDesc), hipMemcpyHostToDevice,
                                 ctx->stream);
   if (e == hipSuccess) e = hipEventRecord(copied_, ctx->stream);
-  if (e != hipSuccess) return from_hip(e);
+  if (e != hipSuccess) {
+    if (graph) (void)hipFree(descs);
+    return from_hip(e);
+  }
+  if (graph) {
+    e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      (void)hipFree(descs);
+      return from_hip(e);
+    }
+  }
   Marks* marks = ctx->prof;
   if (ctx->prof) ctx->prof->begin(ctx->stream);
   for (const Cls& c : cls) {
     TwiddleSet tw;
     rc = get_twiddles(ctx, c.logN, c.sh.logR, &tw);
-    if (rc) return rc;
+    if (rc) break;
     // grid.z is at most 65535: a very large class goes in several launches
-    for (size_t off = 0; off < c.n; off += 65535) {
+    for (size_t off = 0; off < c.n && e == hipSuccess; off += 65535) {
       Work w{};
-      w.many = d_desc_ + c.first + off;
+      w.many = descs + c.first + off;
       w.count = (uint32_t)std::min<size_t>(65535, c.n - off);
       e = launch_forward(w, c.sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
       if (e == hipSuccess) e = launch_inverse(w, c.sh, ctx->cs, tw, ctx->stream, marks);
       if (e == hipSuccess) e = launch_recover(w, c.sh, ctx->cs, ctx->d_div, ctx->stream, marks);
-      if (e != hipSuccess) return from_hip(e);
     }
+    if (e != hipSuccess) break;
   }
-  return DMUL_OK;
+  if (graph) {
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
+    if (e == hipSuccess) e = ec;
+    Graph entry;
+    entry.descs = descs;
+    if (e == hipSuccess && !rc) e = hipGraphInstantiate(&entry.exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e == hipSuccess && !rc) e = hipGraphLaunch(entry.exec, ctx->stream);
+    if (e != hipSuccess || rc) {
+      if (entry.exec) (void)hipGraphExecDestroy(entry.exec);
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipFree(descs);
+      return rc ? rc : from_hip(e);
+    }
+    graphs_[sig] = entry;
+  }
+  if (rc) return rc;
+  return from_hip(e);
 }
 
 }  // namespace dmi

@@ -256,3 +256,33 @@ def test_repeatable(dm, ctx):
     for _ in range(3):
         np.testing.assert_array_equal(dm.to_host(ctx.mul(da, db)), first)
     np.testing.assert_array_equal(first, oracle.mul_ntt(a, b))
+
+
+def test_batch_graph_replays_match(dm):
+    """A batch captured in a HIP graph and replayed several times, with other
+    work on the device in between, gives the eager result on every replay."""
+    import torch
+    _note("batch graph replay")
+    s = torch.cuda.Stream()
+    ctx = dm.Context(0, stream=s)
+    try:
+        rng = random.Random(777)
+        sizes = [(3, 5), (80, 81), (700, 20), (1500, 1499), (64, 64), (33, 4000)]
+        host = [(_rand_limbs(rng, x), _rand_limbs(rng, y)) for x, y in sizes]
+        dev = [(dm.to_device(a), dm.to_device(b)) for a, b in host]
+        torch.cuda.synchronize()
+        want = [oracle.mul_ntt(a, b) for a, b in host]
+        outs = [torch.zeros(a.numel() + b.numel(), dtype=torch.uint64, device="cuda") for a, b in dev]
+        for rep in range(4):
+            for o in outs:
+                o.zero_()
+            torch.cuda.synchronize()
+            _, st = ctx.batch(dev, graph=True, outs=outs)
+            assert st == [0] * len(sizes)
+            for o, w in zip(outs, want):
+                np.testing.assert_array_equal(dm.to_host(o), w)
+            # eager work in between the replays
+            x = dm.to_device(_rand_limbs(rng, 500))
+            np.testing.assert_array_equal(dm.to_host(ctx.mul(x, x)), oracle.mul_ntt(dm.to_host(x), dm.to_host(x)))
+    finally:
+        ctx.close()
