@@ -328,7 +328,7 @@ int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t*
     e = hipMemcpyAsync(residues, ctx->ws, 2 * pl.N * sizeof(uint64_t), hipMemcpyDeviceToDevice, ctx->stream);
     return from_hip(e);
   }
-  e = launch_recover(w, sh, ctx->cs, ctx->d_div, ctx->stream, marks);
+  e = launch_recover(w, sh, ctx->cs, ctx->d_div, &ctx->h_div, ctx->stream, marks);
   return from_hip(e);
 }
 
@@ -434,6 +434,7 @@ int dmul_ctx_create(dmul_ctx** out, int device, size_t budget) {
   if (!c) return DMUL_ENOMEM;
   c->device = device;
   c->budget = budget;
+  c->h_div = dt;
   load_tuning(&c->tune);
   for (int i = 0; i < 2; ++i) {
     c->cs.P[i].p = kP[i];

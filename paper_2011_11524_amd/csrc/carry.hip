@@ -41,6 +41,10 @@ struct RecTable {
   uint64_t r_tilde;
   uint64_t B[6], d[6], v[6];
   uint32_t sh[6], kinv[6];
+  uint64_t Ph[6], Pl[6];      // p1 = Ph*B + Pl
+  uint64_t bmag[6];           // floor(x / B) = umulhi(x >> k, bmag) >> bsh  (x < 2^64)
+  uint32_t bsh[6];
+  double inv_B[6];            // 1/B rounded to double
 };
 
 // What one product's recovery needs, taken from the table by its k.
@@ -53,6 +57,9 @@ struct RecConsts {
   uint64_t v;
   int sh;
   int k;
+  uint64_t Ph, Pl, bmag;
+  uint32_t bsh;
+  double inv_B;
   uint32_t kinv;
   uint32_t nblk;
   uint64_t NP;         // n + m coefficient positions
@@ -70,6 +77,11 @@ __device__ __forceinline__ RecConsts rec_consts(const RecTable& t, const ProdDes
   rc.v = t.v[i];
   rc.sh = (int)t.sh[i];
   rc.kinv = t.kinv[i];
+  rc.Ph = t.Ph[i];
+  rc.Pl = t.Pl[i];
+  rc.bmag = t.bmag[i];
+  rc.bsh = t.bsh[i];
+  rc.inv_B = t.inv_B[i];
   rc.k = d.pl.k;
   rc.nblk = d.nblk;
   rc.NP = d.pl.n + d.pl.m;
@@ -102,26 +114,51 @@ __device__ __forceinline__ void div_2by1(uint64_t u1, uint64_t u0, uint64_t d, u
   r = rr;
 }
 
-// Base-B digits (q0, q1, q2) of coefficient c_i from its two residues:
-// CRT, then c = (q2*B + q1)*B + q0 by three 2-by-1 divisions.
+// x = q*B + r for a 64-bit x (multiply-high by the reciprocal of 10^k).
+__device__ __forceinline__ uint64_t divmod_B64(uint64_t x, const RecConsts& rc, uint64_t& r) {
+  const uint64_t q = __umul64hi(x >> rc.k, rc.bmag) >> rc.bsh;
+  r = x - q * rc.B;
+  return q;
+}
+
+// Base-B digits (q0, q1, q2) of coefficient c_i from its two residues.  The
+// CRT gives c = a1 + p1*phi (Section 8.2.2).  With p1 = Ph*B + Pl,
+// phi = fh*B + fl and a1 = ah*B + al (all digits < B):
+//   c = (al + Pl*fl) + B*(ah + Ph*fl + Pl*fh) + B^2*(Ph*fh)
+// so one 128-by-64 division (of Pl*fl < B^2) and one quotient of a 65-bit
+// value (by a double-precision estimate, corrected exactly) give the digits.
 __device__ __forceinline__ void crt_digits(uint64_t a1, uint64_t a2, const RecConsts& rc,
                                            uint64_t& q0, uint64_t& q1, uint64_t& q2) {
   const uint64_t psi = sub_mod(a2, a1, rc.P2);              // a1 < p1 < p2
   const uint64_t phi = mont_mul(psi, rc.r_tilde, rc.P2);    // r * (a2 - a1) mod p2
+  uint64_t fl, al;
+  const uint64_t fh = divmod_B64(phi, rc, fl);
+  const uint64_t ah = divmod_B64(a1, rc, al);
+  // Pl*fl = th*B + tl
   uint64_t lo, hi;
-  mul_wide(rc.p1, phi, lo, hi);
-  lo += a1;
-  hi += lo < a1 ? 1 : 0;                                    // c = a1 + p1*phi < p1*p2
+  mul_wide(rc.Pl, fl, lo, hi);
   const int sh = rc.sh;                                     // 4 <= sh <= 20
-  uint64_t qh, ql, r1, r0;
-  div_2by1(hi >> (64 - sh), (hi << sh) | (lo >> (64 - sh)), rc.d, rc.v, qh, r1);
-  div_2by1(r1, lo << sh, rc.d, rc.v, ql, r0);
-  q0 = r0 >> sh;
-  // (qh:ql) = c div B < B^2: its quotient by B fits one word
-  uint64_t t, r2;
-  div_2by1((qh << sh) | (ql >> (64 - sh)), ql << sh, rc.d, rc.v, t, r2);
-  q1 = r2 >> sh;
-  q2 = t;
+  uint64_t th, tr;
+  div_2by1((hi << sh) | (lo >> (64 - sh)), lo << sh, rc.d, rc.v, th, tr);
+  uint64_t s0 = al + (tr >> sh);                            // < 2B
+  const uint64_t c0 = s0 >= rc.B ? 1 : 0;
+  s0 -= c0 * rc.B;
+  q0 = s0;
+  // mid = ah + Ph*fl + Pl*fh + th + c0 < 2^65, as (mh:ml)
+  const uint64_t x = rc.Ph * fl, y = rc.Pl * fh;            // each < 2^63
+  uint64_t ml = x + y;
+  uint64_t mh = ml < x ? 1 : 0;
+  const uint64_t z = th + ah + c0;                          // < 2^61
+  ml += z;
+  mh += ml < z ? 1 : 0;
+  // q = floor(mid / B) from a double estimate (error well below 1), then exact
+  const double md = (double)mh * 18446744073709551616.0 + (double)ml;
+  uint64_t q = (uint64_t)floor(md * rc.inv_B);
+  int64_t r = (int64_t)(ml - q * rc.B);                     // mid - q*B, in (-B, 2B)
+  if (r < 0) { q -= 1; r += (int64_t)rc.B; }
+  else if (r >= (int64_t)rc.B) { q += 1; r -= (int64_t)rc.B; }
+  q1 = (uint64_t)r;
+  q2 = rc.Ph * fh + q;
 }
 
 // Carry maps {0,1,2} -> {0,1,2}, two bits per image: bits [2c, 2c+2) = f(c).
@@ -382,7 +419,7 @@ size_t recover_scratch_words(const PlanDev& pl) {
 }
 
 hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, const DivTable* dt,
-                          hipStream_t st, Marks* marks) {
+                          const DivTable* dt_host, hipStream_t st, Marks* marks) {
   RecTable rt;
   rt.P2 = cs.P[1];
   rt.p1 = cs.P[0].p;
@@ -396,6 +433,11 @@ hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, cons
     rt.d[i] = B << rt.sh[i];
     rt.v[i] = (uint64_t)((~(u128)0) / rt.d[i] - ((u128)1 << 64));
     rt.kinv[i] = (uint32_t)(((1u << 22) + k - 1) / k);
+    rt.Ph[i] = rt.p1 / B;
+    rt.Pl[i] = rt.p1 % B;
+    rt.bmag[i] = dt_host->mag[k];
+    rt.bsh[i] = dt_host->sh[k];
+    rt.inv_B[i] = 1.0 / (double)B;
   }
   hipLaunchKernelGGL(k_rec_crt<kRecPT>, dim3(sh.max_nblk, 1, w.count), dim3(kRecThreads + 1), 0, st, w, rt);
   if (marks) marks->mark(kRecCrt, st);

@@ -83,6 +83,7 @@ struct dmul_ctx {
   size_t budget = 0;
   Consts cs{};
   DivTable* d_div = nullptr;
+  DivTable h_div{};                     // host copy of the power-of-ten reciprocals
   uint64_t* d_roots = nullptr;          // [prime][dir] blocks of 2^kMaxLogLen - 1 words
   std::map<int, dmi::PassTables> pass; // by log2 N
   uint64_t* ws = nullptr;

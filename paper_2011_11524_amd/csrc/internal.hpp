@@ -98,7 +98,7 @@ hipError_t launch_forward(const Work& w, const Shape& sh, const Consts& cs, cons
 hipError_t launch_inverse(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                           hipStream_t stream, Marks* marks);
 hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, const DivTable* dt,
-                          hipStream_t stream, Marks* marks);
+                          const DivTable* dt_host, hipStream_t stream, Marks* marks);
 size_t recover_blocks(const PlanDev& pl);
 size_t recover_scratch_words(const PlanDev& pl);
 hipError_t launch_zero(uint64_t* out, size_t n, hipStream_t stream);
