@@ -46,21 +46,27 @@ OPS_LAZYSUB = 3
 OPS_DIF = OPS_MODADD + OPS_LAZYSUB + OPS_MODMUL     # x+y, (x-y+p)*w
 OPS_DIT = OPS_MODMUL + 2 * OPS_MODADD              # u = y*w, x+u, x-u
 OPS_BF1 = 2 * OPS_MODADD                           # factor 1: x+y, x-y
+# radix-3 butterfly of a row of 3M points, per triple: b+c, a+(b+c), a halving
+# (5), a-(b+c)/2, b-c+p, kappa*(b-c), m+v, m-v, and the two twiddle products
+OPS_R3 = 5 * OPS_MODADD + 5 + OPS_LAZYSUB + 3 * OPS_MODMUL
 OPS_SPLIT = 24      # two multiply-high divisions by powers of ten per group
 OPS_CRT = 120       # CRT modmul, 64x64 product, four 2-by-1 divisions
 OPS_CARRY = 12      # per position: carry map, scan step, digit
 
 
-def phase_work(N: int, logR: int, logC: int, arrays_fwd: int, NP: int, na: int, nb: int) -> dict:
-    """Algorithmic VALU operations and HBM bytes of each kernel phase."""
+def phase_work(N: int, logR: int, logC: int, factor: int, arrays_fwd: int, NP: int, na: int,
+               nb: int) -> dict:
+    """Algorithmic VALU operations and HBM bytes of each kernel phase of a
+    length-N transform laid out as 2^logR rows of factor * 2^logC points."""
     half = N // 2
     fwd_stage = lambda logl: half * (OPS_BF1 + (logl - 1) * OPS_DIF)
     inv_stage = lambda logl: half * (OPS_BF1 + (logl - 1) * OPS_DIT)
+    r3 = (N // 3) * OPS_R3 if factor == 3 else 0
     w = {}
     w["fwd_cols"] = (arrays_fwd * (fwd_stage(logR) + N * (2 * OPS_MODMUL + OPS_SPLIT)),
                      2 * 8 * (na + nb) + arrays_fwd * 8 * N)
-    w["fwd_rows"] = (arrays_fwd * fwd_stage(logC), arrays_fwd * 16 * N)
-    w["inv_rows"] = (2 * (N * OPS_MODMUL + inv_stage(logC)), 2 * 24 * N)
+    w["fwd_rows"] = (arrays_fwd * (fwd_stage(logC) + r3), arrays_fwd * 16 * N)
+    w["inv_rows"] = (2 * (N * OPS_MODMUL + inv_stage(logC) + r3), 2 * 24 * N)
     w["inv_cols"] = (2 * (2 * N * OPS_MODMUL + inv_stage(logR)), 2 * 16 * N)
     w["rec_crt"] = (NP * OPS_CRT, 24 * NP)
     w["rec_apply"] = (NP * OPS_CARRY, 8 * NP + 8 * (na + nb))
@@ -129,7 +135,7 @@ def run_batched(dm, ctx, torch, steps: int, warmup: int, count: int):
         outs_a.append(torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda"))
         outs_b.append(torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda"))
         digits += int(x) + int(y)
-    logn = [dm.plan(len(a), len(b)).log2_n for a, b in host]
+    lens = [dm.plan(len(a), len(b)).N for a, b in host]
 
     def one_by_one():
         for (ta, tb), o in zip(pairs, outs_a):
@@ -149,7 +155,7 @@ def run_batched(dm, ctx, torch, steps: int, warmup: int, count: int):
     gctx = dm.Context(0, stream=torch.cuda.Stream())
 
     res = {"products": count, "digits": digits,
-           "size_classes": {int(k): int(v) for k, v in zip(*np.unique(logn, return_counts=True))}}
+           "size_classes": {int(k): int(v) for k, v in zip(*np.unique(lens, return_counts=True))}}
     for name, fn in (("per_product", one_by_one), ("batched", batched), ("batched_graph", batched_graph)):
         for _ in range(warmup):
             fn()
@@ -168,9 +174,9 @@ def run_batched(dm, ctx, torch, steps: int, warmup: int, count: int):
     batched()
     ev = [t for ph, t in ctx.profile_events() if ph == "rec_apply"]
     ctx.profile(False)
-    classes = sorted(set(logn))
+    classes = sorted(set(lens))
     done = {c: ev[i] for i, c in enumerate(classes)} if len(ev) == len(classes) else {}
-    lat_b = [done[c] for c in logn] if done else []
+    lat_b = [done[c] for c in lens] if done else []
     for name, lat in (("per_product", lat_pp), ("batched", lat_b)):
         res[name]["p50_ms"] = _pct(lat, 50)
         res[name]["p99_ms"] = _pct(lat, 99)
@@ -247,6 +253,8 @@ def main() -> int:
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--serving", action="store_true", help="also run the serving workload")
     ap.add_argument("--requests", type=int, default=100_000)
+    ap.add_argument("--pow2", action="store_true",
+                    help="power-of-two transform length even where 3*2^e is shorter")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size (counter calibration)")
     args = ap.parse_args()
@@ -272,18 +280,18 @@ def main() -> int:
     D = args.digits
     a = synth.random_operand(D, 2001)
     b = synth.random_operand(D, 2002)
-    pl = dm.plan(len(a), len(b))
+    pl = dm.plan(len(a), len(b), pow2=args.pow2)
     ta, tb = dm.to_device(a), dm.to_device(b)
     out = torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda")
     ctx = dm.Context(0)
 
     for _ in range(args.warmup):
-        ctx.mul_async(ta, tb, out)
+        ctx.mul_async(ta, tb, out, pow2=args.pow2)
     ctx.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.mul_async(ta, tb, out)
+        ctx.mul_async(ta, tb, out, pow2=args.pow2)
     ctx.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -294,12 +302,12 @@ def main() -> int:
     # per-kernel durations (events on the context stream), a separate pass
     ctx.profile(True)
     for _ in range(args.steps):
-        ctx.mul_async(ta, tb, out)
+        ctx.mul_async(ta, tb, out, pow2=args.pow2)
     ctx.sync()
     prof = ctx.profile_read()
     ctx.profile(False)
     NP = pl.groups_a + pl.groups_b
-    work = phase_work(pl.N, pl.log2_rows, pl.log2_cols, 4, NP, len(a), len(b))
+    work = phase_work(pl.N, pl.log2_rows, pl.log2_cols, pl.factor, 4, NP, len(a), len(b))
     phases = {}
     for name, (ms, cnt) in prof.items():
         if cnt == 0:
@@ -340,7 +348,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"exact product of two random {D}-digit integers (base-10^19 limbs)",
                    "digits_a": D, "digits_b": D, "limbs_a": len(a), "limbs_b": len(b),
-                   "k": pl.k, "N": pl.N, "layout": f"{1 << pl.log2_rows}x{1 << pl.log2_cols}",
+                   "k": pl.k, "N": pl.N, "layout": f"{1 << pl.log2_rows}x{pl.factor << pl.log2_cols}",
                    "seeds": [2001, 2002]},
         "roofline": roofline,
         "hbm": hbm,

@@ -16,8 +16,9 @@
  * into base-10^k digit groups with the largest k in [13, 18] such that
  * (10^k - 1)^2 * min(n_k, m_k) < p1 * p2 (eq. ci_bound as the range
  * condition of eq. product_inequality; n_k = ceil(19 na / k) counts every
- * limb as 19 digits), the groups are convolved cyclically at the length
- * N = 2^ceil(log2(n_k + m_k)) (Section 3.2) modulo the two primes
+ * limb as 19 digits), the groups are convolved cyclically at the length N,
+ * the shortest 2^e or 3 * 2^e that holds n_k + m_k coefficients (Sections
+ * 3.2 and 7.8), modulo the two primes
  *   p1 = 9223371564408373249 = 1073741769 * 2^33 + 1,
  *   p2 = 9223371938070528001 = 2147483625 * 2^32 + 1
  * (the two largest primes c*3*2^n + 1 < 2^63 with c odd and n >= 32,
@@ -70,19 +71,29 @@ extern "C" {
  * one the flag is ignored.  Captured batches are dropped when the context's
  * batch buffers grow (at most 8 are kept). */
 #define DMUL_FLAG_GRAPH 0x100u
+/* Use a power-of-two transform length even where 3 * 2^e is shorter (for
+ * tests and comparisons; the product is the same). */
+#define DMUL_FLAG_POW2 0x200u
 
 typedef struct dmul_ctx dmul_ctx;
 
-/* Plan of one product, as chosen by the library (Section 3.2 padding rule,
- * Section 7.9 split N = R * C with R = 2^floor(log2 N / 2)). */
+/* Plan of one product, as chosen by the library: Section 3.2 padding to a
+ * length N = factor * 2^log2_n (factor 1, or 3 as in Section 7.8), laid out
+ * as R x C (Section 7.9) with R = 2^log2_rows rows and
+ * C = factor * 2^log2_cols columns, log2_rows + log2_cols = log2_n, and
+ * log2_rows = floor(log2_n / 2) except where a row of 3 * 2^log2_cols
+ * points would pass 6144 points. */
 typedef struct dmul_plan_info {
   int32_t k;            /* decimal digits per group */
-  int32_t log2_n;       /* N = 2^log2_n */
-  int32_t log2_rows;    /* R */
-  int32_t log2_cols;    /* C */
+  int32_t log2_n;
+  int32_t log2_rows;
+  int32_t log2_cols;
   uint64_t groups_a;    /* n_k */
   uint64_t groups_b;    /* m_k */
   uint64_t workspace_bytes;
+  uint64_t transform_len;  /* N */
+  int32_t factor;          /* 1 or 3 */
+  int32_t reserved;
 } dmul_plan_info;
 
 /* dmul: Z = X * Y, blocking.  a, b, out: device pointers on the current HIP
@@ -169,13 +180,14 @@ int dmul_ctx_profile_read(dmul_ctx* ctx, double* total_ms, uint64_t* launches, i
 int dmul_ctx_profile_events(dmul_ctx* ctx, int32_t* phases, double* end_ms, int n);
 const char* dmul_phase_name(int phase);
 
-/* Size-class tuning: for products of transform length 2^log2_n, every
- * workgroup of the row pass loops over `row_iters` groups of rows (0 = the
- * default).  Contexts start from the table written by the project's
- * autotuner (dmul_tune.txt beside the library, or the file named by
- * DMUL_TUNE_TABLE: lines "log2_n row_iters").  Returns DMUL_OK or
- * DMUL_EINVAL. */
-int dmul_ctx_tune(dmul_ctx* ctx, int log2_n, int row_iters);
+/* Size-class tuning: for products of transform length transform_len
+ * (2^e or 3 * 2^e), every workgroup of the row pass loops over `row_iters`
+ * groups of rows (0 = the default).  Contexts start from the table written
+ * by the project's autotuner (dmul_tune.txt beside the library, or the file
+ * named by DMUL_TUNE_TABLE: lines "transform_len row_iters").  Returns
+ * DMUL_OK or DMUL_EINVAL (a length that is not a supported size class, or
+ * row_iters outside 0..64). */
+int dmul_ctx_tune(dmul_ctx* ctx, uint64_t transform_len, int row_iters);
 
 /* Library version string. */
 const char* dmul_version(void);

@@ -29,6 +29,7 @@ DMUL_ERANGE = -3
 DMUL_ENOMEM = -4
 DMUL_EDEVICE = -5
 DMUL_FLAG_GRAPH = 0x100
+DMUL_FLAG_POW2 = 0x200
 
 # Every function the header declares (checked by the test suite).
 EXPORTS = ("dmul", "dmul_ctx_create", "dmul_ctx_destroy", "dmul_ctx_set_stream", "dmul_ex",
@@ -47,11 +48,14 @@ class DmulError(RuntimeError):
 class _PlanInfo(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("log2_n", ctypes.c_int32), ("log2_rows", ctypes.c_int32),
                 ("log2_cols", ctypes.c_int32), ("groups_a", ctypes.c_uint64),
-                ("groups_b", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64)]
+                ("groups_b", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64),
+                ("transform_len", ctypes.c_uint64), ("factor", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 @dataclass
 class Plan:
+    """N = factor * 2^log2_n as R x C, R = 2^log2_rows, C = factor * 2^log2_cols."""
     k: int
     log2_n: int
     log2_rows: int
@@ -59,10 +63,8 @@ class Plan:
     groups_a: int
     groups_b: int
     workspace_bytes: int
-
-    @property
-    def N(self) -> int:
-        return 1 << self.log2_n
+    N: int
+    factor: int
 
 
 _lib = None
@@ -104,7 +106,7 @@ def lib():
                                         ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
     L.dmul_ctx_profile_events.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int]
-    L.dmul_ctx_tune.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.dmul_ctx_tune.argtypes = [vp, ctypes.c_uint64, ctypes.c_int]
     L.dmul_phase_name.argtypes = [ctypes.c_int]
     L.dmul_phase_name.restype = ctypes.c_char_p
     _lib = L
@@ -118,8 +120,8 @@ def strerror(code: int) -> str:
         return f"dmul status {code}"
 
 
-def flags_for(force_k: int = 0) -> int:
-    return int(force_k) & 0x1F
+def flags_for(force_k: int = 0, pow2: bool = False) -> int:
+    return (int(force_k) & 0x1F) | (DMUL_FLAG_POW2 if pow2 else 0)
 
 
 def primes() -> tuple[list[int], list[int]]:
@@ -129,13 +131,13 @@ def primes() -> tuple[list[int], list[int]]:
     return [int(p[0]), int(p[1])], [int(g[0]), int(g[1])]
 
 
-def plan(na: int, nb: int, force_k: int = 0) -> Plan:
+def plan(na: int, nb: int, force_k: int = 0, pow2: bool = False) -> Plan:
     info = _PlanInfo()
-    rc = lib().dmul_plan(int(na), int(nb), flags_for(force_k), ctypes.byref(info))
+    rc = lib().dmul_plan(int(na), int(nb), flags_for(force_k, pow2), ctypes.byref(info))
     if rc:
         raise DmulError(rc, "dmul_plan")
     return Plan(info.k, info.log2_n, info.log2_rows, info.log2_cols, info.groups_a,
-                info.groups_b, info.workspace_bytes)
+                info.groups_b, info.workspace_bytes, info.transform_len, info.factor)
 
 
 def workspace_bytes(na: int, nb: int) -> int:
@@ -188,7 +190,7 @@ class Context:
         self.close()
 
     # -- single products ----------------------------------------------------
-    def mul_async(self, a, b, out, force_k: int = 0) -> None:
+    def mul_async(self, a, b, out, force_k: int = 0, pow2: bool = False) -> None:
         _check_limbs(a, "a")
         _check_limbs(b, "b")
         _check_limbs(out, "out")
@@ -196,7 +198,7 @@ class Context:
             raise ValueError("out must hold len(a) + len(b) limbs")
         rc = self._lib.dmul_ex(self._h, ctypes.c_void_p(a.data_ptr()), a.numel(),
                                ctypes.c_void_p(b.data_ptr()), b.numel(),
-                               ctypes.c_void_p(out.data_ptr()), flags_for(force_k))
+                               ctypes.c_void_p(out.data_ptr()), flags_for(force_k, pow2))
         if rc:
             raise DmulError(rc, "dmul_ex")
 
@@ -205,15 +207,16 @@ class Context:
         if rc:
             raise DmulError(rc, "dmul_sync")
 
-    def mul(self, a, b, force_k: int = 0, out=None):
+    def mul(self, a, b, force_k: int = 0, out=None, pow2: bool = False):
         if out is None:
             out = torch.empty(a.numel() + b.numel(), dtype=torch.uint64, device=a.device)
-        self.mul_async(a, b, out, force_k)
+        self.mul_async(a, b, out, force_k, pow2)
         self.sync()
         return out
 
     # -- batches -------------------------------------------------------------
-    def batch_async(self, pairs: Sequence, outs: Sequence, force_k: int = 0, graph: bool = False):
+    def batch_async(self, pairs: Sequence, outs: Sequence, force_k: int = 0, graph: bool = False,
+                    pow2: bool = False):
         """Enqueue len(pairs) products (a_i, b_i) -> outs[i]; returns the host
         status array that sync() fills in.  graph=True captures the batch in
         a HIP graph, replayed when the same batch is submitted again."""
@@ -230,23 +233,24 @@ class Context:
             O[i] = o.data_ptr() if o.numel() else 0
             NA[i] = a.numel()
             NB[i] = b.numel()
-        flags = flags_for(force_k) | (DMUL_FLAG_GRAPH if graph else 0)
+        flags = flags_for(force_k, pow2) | (DMUL_FLAG_GRAPH if graph else 0)
         rc = self._lib.dmul_batch(self._h, n, A, NA, B, NB, O, st, flags)
         if rc:
             raise DmulError(rc, "dmul_batch")
         self._keep = (A, B, O, NA, NB)
         return st
 
-    def batch(self, pairs: Sequence, force_k: int = 0, graph: bool = False, outs=None):
+    def batch(self, pairs: Sequence, force_k: int = 0, graph: bool = False, outs=None,
+              pow2: bool = False):
         if outs is None:
             outs = [torch.empty(a.numel() + b.numel(), dtype=torch.uint64, device=a.device)
                     for a, b in pairs]
-        st = self.batch_async(pairs, outs, force_k, graph)
+        st = self.batch_async(pairs, outs, force_k, graph, pow2)
         self.sync()
         return outs, [int(s) for s in st]
 
-    def tune(self, log2_n: int, row_iters: int) -> None:
-        rc = self._lib.dmul_ctx_tune(self._h, int(log2_n), int(row_iters))
+    def tune(self, transform_len: int, row_iters: int) -> None:
+        rc = self._lib.dmul_ctx_tune(self._h, int(transform_len), int(row_iters))
         if rc:
             raise DmulError(rc, "dmul_ctx_tune")
 
@@ -277,14 +281,14 @@ class Context:
         return [(self._lib.dmul_phase_name(ph[i]).decode(), float(t[i])) for i in range(n)]
 
     # -- debug view of the convolution ---------------------------------------
-    def residues(self, a, b, force_k: int = 0):
+    def residues(self, a, b, force_k: int = 0, pow2: bool = False):
         """The cyclic convolution of the digit groups of a and b mod p1 and mod
         p2 (two length-N uint64 tensors)."""
-        pl = plan(a.numel(), b.numel(), force_k)
+        pl = plan(a.numel(), b.numel(), force_k, pow2)
         res = torch.empty(2 * pl.N, dtype=torch.uint64, device=a.device)
         rc = self._lib.dmul_debug_residues(self._h, ctypes.c_void_p(a.data_ptr()), a.numel(),
                                            ctypes.c_void_p(b.data_ptr()), b.numel(),
-                                           ctypes.c_void_p(res.data_ptr()), flags_for(force_k))
+                                           ctypes.c_void_p(res.data_ptr()), flags_for(force_k, pow2))
         if rc:
             raise DmulError(rc, "dmul_debug_residues")
         return res[: pl.N], res[pl.N:]
@@ -300,15 +304,15 @@ def to_host(t) -> np.ndarray:
     return t.cpu().numpy()
 
 
-def mul(a, b, force_k: int = 0):
+def mul(a, b, force_k: int = 0, pow2: bool = False):
     """Z = X * Y with the device's default context (blocking).  a, b: CUDA
     uint64 tensors; returns a new tensor of len(a) + len(b) limbs."""
     _check_limbs(a, "a")
     _check_limbs(b, "b")
     out = torch.empty(a.numel() + b.numel(), dtype=torch.uint64, device=a.device)
-    if force_k:
+    if force_k or pow2:
         ctx = _default_context(a.device.index or 0)
-        return ctx.mul(a, b, force_k, out)
+        return ctx.mul(a, b, force_k, out, pow2)
     with torch.cuda.device(a.device):
         rc = lib().dmul(ctypes.c_void_p(a.data_ptr() if a.numel() else 0), a.numel(),
                         ctypes.c_void_p(b.data_ptr() if b.numel() else 0), b.numel(),
@@ -318,14 +322,14 @@ def mul(a, b, force_k: int = 0):
     return out
 
 
-def mul_host(a, b, force_k: int = 0, device: int = 0) -> np.ndarray:
+def mul_host(a, b, force_k: int = 0, device: int = 0, pow2: bool = False) -> np.ndarray:
     """Host-array convenience (copies in and out); for tests and tools."""
     a = np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
     b = np.ascontiguousarray(np.asarray(b, dtype=np.uint64))
     out = np.zeros(len(a) + len(b), dtype=np.uint64)
     u64p = ctypes.POINTER(ctypes.c_uint64)
     rc = lib().dmul_host(int(device), a.ctypes.data_as(u64p), len(a), b.ctypes.data_as(u64p), len(b),
-                         out.ctypes.data_as(u64p), flags_for(force_k))
+                         out.ctypes.data_as(u64p), flags_for(force_k, pow2))
     if rc:
         raise DmulError(rc, "dmul_host")
     return out

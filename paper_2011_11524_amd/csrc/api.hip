@@ -121,7 +121,7 @@ namespace dmi {
 int from_hip(hipError_t e) { return e == hipSuccess ? DMUL_OK : (e == hipErrorOutOfMemory ? DMUL_ENOMEM : DMUL_EDEVICE); }
 
 int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl) {
-  if (flags & ~DMUL_FLAG_K_MASK) return DMUL_EINVAL;
+  if (flags & ~(DMUL_FLAG_K_MASK | DMUL_FLAG_POW2)) return DMUL_EINVAL;
   const int fk = (int)(flags & DMUL_FLAG_K_MASK);
   if (fk && (fk < kMinK || fk > 18)) return DMUL_EINVAL;
   if (na == 0 || nb == 0) return DMUL_EINVAL;
@@ -141,58 +141,78 @@ int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl) {
     if (L <= (P - 1) / mn) { k = kk; nk = a; mk = b; break; }
   }
   if (!k) return DMUL_ERANGE;
-  int logN = 0;
-  while (((uint64_t)1 << logN) < nk + mk) ++logN;
-  if (logN < 2) logN = 2;
-  if (logN > kMaxLogN) return DMUL_ERANGE;
+  // Transform length: the shortest 2^e or 3*2^e (Section 7.8) holding all
+  // n_k + m_k coefficients (Section 3.2); each layout within its LDS limits.
+  const uint64_t need = nk + mk;
+  int e2 = 2;
+  while (((uint64_t)1 << e2) < need) ++e2;
+  int e3 = kMinLogN3;
+  while (((uint64_t)3 << e3) < need) ++e3;
+  int logR3 = e3 / 2;
+  if (e3 - logR3 > kMaxLogC3) logR3 = e3 - kMaxLogC3;
+  const bool fit3 = logR3 <= kMaxLogR3;
+  const bool fit2 = e2 <= kMaxLogN;
+  const bool use3 = !(flags & DMUL_FLAG_POW2) && fit3 && (!fit2 || ((uint64_t)3 << e3) < ((uint64_t)1 << e2));
+  if (!use3 && !fit2) return DMUL_ERANGE;
   pl->na = na;
   pl->nb = nb;
   pl->n = nk;
   pl->m = mk;
   pl->k = k;
-  pl->logN = logN;
-  pl->N = (uint64_t)1 << logN;
-  pl->logR = logN / 2;
-  pl->logC = logN - pl->logR;
+  if (use3) {
+    pl->rad3 = 1;
+    pl->logN = e3;
+    pl->N = (uint64_t)3 << e3;
+    pl->logR = logR3;
+  } else {
+    pl->rad3 = 0;
+    pl->logN = e2;
+    pl->N = (uint64_t)1 << e2;
+    pl->logR = e2 / 2;
+  }
+  pl->logC = pl->logN - pl->logR;
   return DMUL_OK;
 }
 
 size_t workspace_words(const PlanDev& pl) { return 4 * (size_t)pl.N; }
 
 // Builds (once per length) the inter-pass factor tables of a transform of
-// length N = R*C and returns pointers to them.
-int get_twiddles(dmul_ctx* ctx, int logN, int logR, TwiddleSet* tw) {
+// length N = R*C and returns pointers to them: xi_N^(+-e) for e < N as
+// hi[e >> lb] * lo[e mod 2^lb], lb = pass_split_bits.
+int get_twiddles(dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw) {
   const size_t L1 = ((size_t)1 << kMaxLogLen) - 1;
   for (int i = 0; i < 2; ++i) {
     tw->len_fwd[i] = ctx->d_roots + (size_t)(2 * i) * L1;
     tw->len_inv[i] = ctx->d_roots + (size_t)(2 * i + 1) * L1;
+    tw->r3_fwd[i] = ctx->d_r3 + (size_t)(2 * i) * kR3TableWords;
+    tw->r3_inv[i] = ctx->d_r3 + (size_t)(2 * i + 1) * kR3TableWords;
   }
-  const int logC = logN - logR;
-  const size_t R = (size_t)1 << logR, C = (size_t)1 << logC, N = R * C;
-  auto it = ctx->pass.find(logN);
+  const int lb = pass_split_bits(pl.logC, pl.rad3);
+  const size_t N = pl.N, LO = (size_t)1 << lb, HI = N >> lb;
+  const size_t per = 2 * (HI + LO);
+  auto it = ctx->pass.find(N);
   if (it == ctx->pass.end()) {
-    std::vector<uint64_t> h(2 * (2 * R + 2 * C));
+    std::vector<uint64_t> h(2 * per);
     for (int i = 0; i < 2; ++i) {
       const uint64_t p = kP[i];
       const uint64_t xi = powmod(kG[i], (p - 1) / N, p);   // primitive N-th root
       const uint64_t xinv = inv_mod(xi, p);
       const uint64_t scale = mulmod(to_mont(1, p), inv_mod(N % p, p), p);   // R * N^-1
-      uint64_t* base = h.data() + (size_t)i * (2 * R + 2 * C);
-      uint64_t* hf = base;
-      uint64_t* lf = hf + R;
-      uint64_t* hi = lf + C;
-      uint64_t* li = hi + R;
-      const uint64_t xiC = powmod(xi, C, p), xinvC = powmod(xinv, C, p);
+      uint64_t* hf = h.data() + (size_t)i * per;
+      uint64_t* lf = hf + HI;
+      uint64_t* hi = lf + LO;
+      uint64_t* li = hi + HI;
+      const uint64_t xiS = powmod(xi, LO, p), xinvS = powmod(xinv, LO, p);
       uint64_t a = 1, b = 1;
-      for (size_t e = 0; e < R; ++e) {
+      for (size_t e = 0; e < HI; ++e) {
         hf[e] = to_mont(a, p);
         hi[e] = to_mont(b, p);
-        a = mulmod(a, xiC, p);
-        b = mulmod(b, xinvC, p);
+        a = mulmod(a, xiS, p);
+        b = mulmod(b, xinvS, p);
       }
       a = 1;
       b = 1;
-      for (size_t e = 0; e < C; ++e) {
+      for (size_t e = 0; e < LO; ++e) {
         lf[e] = to_mont(a, p);
         li[e] = to_mont(mulmod(b, scale, p), p);
         a = mulmod(a, xi, p);
@@ -207,14 +227,14 @@ int get_twiddles(dmul_ctx* ctx, int logN, int logR, TwiddleSet* tw) {
       (void)hipFree(pt.dev);
       return from_hip(e);
     }
-    it = ctx->pass.emplace(logN, pt).first;
+    it = ctx->pass.emplace(N, pt).first;
   }
   for (int i = 0; i < 2; ++i) {
-    const uint64_t* base = it->second.dev + (size_t)i * (2 * R + 2 * C);
+    const uint64_t* base = it->second.dev + (size_t)i * per;
     tw->hi_fwd[i] = base;
-    tw->lo_fwd[i] = base + R;
-    tw->hi_inv[i] = base + R + C;
-    tw->lo_inv[i] = base + 2 * R + C;
+    tw->lo_fwd[i] = base + HI;
+    tw->hi_inv[i] = base + HI + LO;
+    tw->lo_inv[i] = base + 2 * HI + LO;
   }
   return DMUL_OK;
 }
@@ -272,9 +292,22 @@ int ensure_rec_sync(dmul_ctx* ctx, size_t words) {
   return DMUL_OK;
 }
 
-int row_iters_for(const dmul_ctx* ctx, int logN) {
-  if (logN >= 0 && logN <= kMaxLogN && ctx->tune.row_iters[logN] > 0) return ctx->tune.row_iters[logN];
-  return 1;
+// N = 2^e (rad3 = 0) or 3 * 2^e (rad3 = 1), a length the planner can choose.
+bool size_class(uint64_t N, int* rad3, int* e) {
+  int r = 0;
+  if (N % 3 == 0) { N /= 3; r = 1; }
+  if (N == 0 || (N & (N - 1))) return false;
+  int l = 0;
+  while (((uint64_t)1 << l) < N) ++l;
+  if (l > kMaxLogN || (r && (l < kMinLogN3 || l > kMaxLogR3 + kMaxLogC3))) return false;
+  *rad3 = r;
+  *e = l;
+  return true;
+}
+
+int row_iters_for(const dmul_ctx* ctx, const PlanDev& pl) {
+  const int v = ctx->tune.row_iters[pl.rad3 ? 1 : 0][pl.logN];
+  return v > 0 ? v : 1;
 }
 
 static bool overlaps(const uint64_t* x, size_t nx, const uint64_t* y, size_t ny) {
@@ -299,7 +332,7 @@ int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t*
   int rc = make_plan(na, nb, flags, &pl);
   if (rc) return rc;
   TwiddleSet tw;
-  rc = get_twiddles(ctx, pl.logN, pl.logR, &tw);
+  rc = get_twiddles(ctx, pl, &tw);
   if (rc) return rc;
   rc = ensure_workspace(ctx, workspace_words(pl));
   if (rc) return rc;
@@ -318,7 +351,7 @@ int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t*
   d.square = (a == b && na == nb) ? 1 : 0;
   w.many = nullptr;
   w.count = 1;
-  Shape sh{pl.logR, pl.logC, d.square ? 0 : 1, row_iters_for(ctx, pl.logN), d.nblk};
+  Shape sh{pl.logR, pl.logC, pl.rad3, d.square ? 0 : 1, row_iters_for(ctx, pl), d.nblk};
   Marks* marks = ctx->prof;
   if (ctx->prof) ctx->prof->begin(ctx->stream);
   hipError_t e = launch_forward(w, sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
@@ -333,8 +366,8 @@ int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t*
 }
 
 // The size-class tuning table: DMUL_TUNE_TABLE, else dmul_tune.txt next to
-// the library.  Lines "log2N row_iters" ('#' starts a comment); missing or
-// unreadable tables leave the defaults.
+// the library.  Lines "N row_iters" ('#' starts a comment); missing or
+// unreadable tables, and lines that name no size class, leave the defaults.
 void load_tuning(TuneTable* t) {
   std::string path;
   if (const char* e = getenv("DMUL_TUNE_TABLE")) {
@@ -353,10 +386,10 @@ void load_tuning(TuneTable* t) {
   char line[256];
   while (fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
-    int logn = 0, iters = 0;
-    if (sscanf(line, "%d %d", &logn, &iters) == 2 && logn >= 0 && logn <= kMaxLogN && iters > 0 &&
-        iters <= 64)
-      t->row_iters[logn] = iters;
+    unsigned long long n = 0;
+    int iters = 0, r3 = 0, e = 0;
+    if (sscanf(line, "%llu %d", &n, &iters) == 2 && size_class(n, &r3, &e) && iters > 0 && iters <= 64)
+      t->row_iters[r3][e] = iters;
   }
   fclose(f);
 }
@@ -412,6 +445,9 @@ int dmul_plan(size_t na, size_t nb, unsigned flags, dmul_plan_info* info) {
   info->groups_a = pl.n;
   info->groups_b = pl.m;
   info->workspace_bytes = workspace_words(pl) * sizeof(uint64_t);
+  info->transform_len = pl.N;
+  info->factor = pl.rad3 ? 3 : 1;
+  info->reserved = 0;
   return DMUL_OK;
 }
 
@@ -460,9 +496,38 @@ int dmul_ctx_create(dmul_ctx** out, int device, size_t budget) {
       }
     }
   }
+  // radix-3 row tables: for every row length C = 3 * 2^l, l = 0..kMaxLogC3,
+  // w_C^i (i < 2^(l+1)), forward and inverse; and the butterfly constant
+  // kappa = (w - w^2) / 2 for the cube root of unity w of each direction.
+  std::vector<uint64_t> r3(4 * kR3TableWords);
+  for (int i = 0; i < 2; ++i) {
+    const uint64_t p = kP[i];
+    for (int l = 0; l <= kMaxLogC3; ++l) {
+      const uint64_t w = powmod(kG[i], (p - 1) / ((uint64_t)3 << l), p);
+      const uint64_t wi = inv_mod(w, p);
+      uint64_t* f = r3.data() + (size_t)(2 * i) * kR3TableWords + r3_table_offset(l);
+      uint64_t* g = r3.data() + (size_t)(2 * i + 1) * kR3TableWords + r3_table_offset(l);
+      uint64_t x = 1, y = 1;
+      for (size_t j = 0; j < ((size_t)2 << l); ++j) {
+        f[j] = to_mont(x, p);
+        g[j] = to_mont(y, p);
+        x = mulmod(x, w, p);
+        y = mulmod(y, wi, p);
+      }
+    }
+    const uint64_t inv2 = (p + 1) / 2;
+    const uint64_t w3 = powmod(kG[i], (p - 1) / 3, p);
+    for (int dir = 0; dir < 2; ++dir) {
+      const uint64_t w = dir ? inv_mod(w3, p) : w3;
+      const uint64_t w2 = mulmod(w, w, p);
+      c->cs.kappa[i][dir] = to_mont(mulmod((w + p - w2) % p, inv2, p), p);
+    }
+  }
   int rc = DMUL_OK;
   e = hipMalloc(&c->d_roots, roots.size() * sizeof(uint64_t));
   if (e == hipSuccess) e = hipMemcpy(c->d_roots, roots.data(), roots.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&c->d_r3, r3.size() * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMemcpy(c->d_r3, r3.data(), r3.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&c->d_div, sizeof(DivTable));
   if (e == hipSuccess) e = hipMemcpy(c->d_div, &dt, sizeof(DivTable), hipMemcpyHostToDevice);
   if (e != hipSuccess) rc = from_hip(e);
@@ -485,6 +550,7 @@ int dmul_ctx_destroy(dmul_ctx* c) {
   for (auto& kv : c->pass) (void)hipFree(kv.second.dev);
   if (c->ws) (void)hipFree(c->ws);
   if (c->d_roots) (void)hipFree(c->d_roots);
+  if (c->d_r3) (void)hipFree(c->d_r3);
   if (c->d_div) (void)hipFree(c->d_div);
   if (c->d_status) (void)hipFree(c->d_status);
   if (c->rec_sync) (void)hipFree(c->rec_sync);
@@ -585,10 +651,11 @@ int dmul_debug_residues(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_
   return rc ? rc : rs;
 }
 
-int dmul_ctx_tune(dmul_ctx* c, int log2_n, int row_iters) {
-  if (!c || log2_n < 0 || log2_n > kMaxLogN || row_iters < 0 || row_iters > 64) return DMUL_EINVAL;
+int dmul_ctx_tune(dmul_ctx* c, uint64_t transform_len, int row_iters) {
+  int r3 = 0, e = 0;
+  if (!c || !size_class(transform_len, &r3, &e) || row_iters < 0 || row_iters > 64) return DMUL_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
-  c->tune.row_iters[log2_n] = row_iters;
+  c->tune.row_iters[r3][e] = row_iters;
   if (c->batch) c->batch->forget_graphs();
   return DMUL_OK;
 }
@@ -638,7 +705,7 @@ int dmul_batch(dmul_ctx* c, size_t count, const uint64_t* const* a, const size_t
                const uint64_t* const* b, const size_t* nb, uint64_t* const* out,
                int32_t* status, unsigned flags) {
   if (!c || (count && (!a || !na || !b || !nb || !out || !status))) return DMUL_EINVAL;
-  if (flags & ~(DMUL_FLAG_K_MASK | DMUL_FLAG_GRAPH)) return DMUL_EINVAL;
+  if (flags & ~(DMUL_FLAG_K_MASK | DMUL_FLAG_POW2 | DMUL_FLAG_GRAPH)) return DMUL_EINVAL;
   for (size_t i = 0; i < count; ++i) {
     const int rc = check_args(a[i], na[i], b[i], nb[i], out[i]);
     if (rc) return rc;

@@ -78,7 +78,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
   }
   // plan, and group the products by transform length
   std::vector<PlanDev> plans(count);
-  std::map<int, std::vector<uint32_t>> classes;
+  std::map<uint64_t, std::vector<uint32_t>> classes;   // by transform length N
   size_t ws_words = 0, sync_words = 0, nvalid = 0;
   for (size_t i = 0; i < count; ++i) {
     if (na[i] == 0 || nb[i] == 0) {
@@ -86,12 +86,12 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       if (e != hipSuccess) return from_hip(e);
       continue;
     }
-    const int rc = make_plan(na[i], nb[i], flags & DMUL_FLAG_K_MASK, &plans[i]);
+    const int rc = make_plan(na[i], nb[i], flags & (DMUL_FLAG_K_MASK | DMUL_FLAG_POW2), &plans[i]);
     if (rc) {
       status[i] = rc;
       continue;
     }
-    classes[plans[i].logN].push_back((uint32_t)i);
+    classes[plans[i].N].push_back((uint32_t)i);
     ws_words += workspace_words(plans[i]);
     sync_words += recover_blocks(plans[i]) + 1;
     ++nvalid;
@@ -106,14 +106,15 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
   // the staging buffer may still feed the previous batch's copy
   if (hipEventSynchronize(copied_) != hipSuccess) return DMUL_EDEVICE;
   size_t wofs = 0, sofs = 0, di = 0;
-  struct Cls { int logN; size_t first, n; Shape sh; };
+  struct Cls { PlanDev p0; size_t first, n; Shape sh; };
   std::vector<Cls> cls;
   for (auto& kv : classes) {
-    Cls c{kv.first, di, kv.second.size(), {}};
     const PlanDev& p0 = plans[kv.second[0]];
+    Cls c{p0, di, kv.second.size(), {}};
     c.sh.logR = p0.logR;
     c.sh.logC = p0.logC;
-    c.sh.row_iters = row_iters_for(ctx, p0.logN);
+    c.sh.rad3 = p0.rad3;
+    c.sh.row_iters = row_iters_for(ctx, p0);
     c.sh.any_nonsquare = 0;
     c.sh.max_nblk = 0;
     for (uint32_t i : kv.second) {
@@ -136,7 +137,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
   }
   for (const Cls& c : cls) {                 // tables exist before any capture
     TwiddleSet tw;
-    rc = get_twiddles(ctx, c.logN, c.sh.logR, &tw);
+    rc = get_twiddles(ctx, c.p0, &tw);
     if (rc) return rc;
   }
   // hipGraph replay: a batch identical to a captured one (same operands,
@@ -183,7 +184,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
   if (ctx->prof) ctx->prof->begin(ctx->stream);
   for (const Cls& c : cls) {
     TwiddleSet tw;
-    rc = get_twiddles(ctx, c.logN, c.sh.logR, &tw);
+    rc = get_twiddles(ctx, c.p0, &tw);
     if (rc) break;
     // grid.z is at most 65535: a very large class goes in several launches
     for (size_t off = 0; off < c.n && e == hipSuccess; off += 65535) {

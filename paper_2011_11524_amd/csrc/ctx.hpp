@@ -10,13 +10,14 @@
 
 namespace dmi {
 class BatchEngine;
-// Launch parameters per transform length log2 N, from the size-class tuner
-// (a text table: "log2N row_iters" per line), or defaults.
+// Launch parameters per transform length N = 2^e ([0][e]) or 3 * 2^e
+// ([1][e]), from the size-class tuner (a text table: "N row_iters" per
+// line), or defaults.
 struct TuneTable {
-  int row_iters[kMaxLogN + 1] = {};
+  int row_iters[2][kMaxLogN + 1] = {};
 };
 struct PassTables {
-  uint64_t* dev = nullptr;   // per prime: hi_fwd[R] lo_fwd[C] hi_inv[R] lo_inv[C]
+  uint64_t* dev = nullptr;   // per prime: hi_fwd[N >> lb] lo_fwd[2^lb] hi_inv[N >> lb] lo_inv[2^lb]
 };
 
 // Per-kernel event timing (dmul_ctx_profile): an event before the first
@@ -85,7 +86,8 @@ struct dmul_ctx {
   DivTable* d_div = nullptr;
   DivTable h_div{};                     // host copy of the power-of-ten reciprocals
   uint64_t* d_roots = nullptr;          // [prime][dir] blocks of 2^kMaxLogLen - 1 words
-  std::map<int, dmi::PassTables> pass; // by log2 N
+  uint64_t* d_r3 = nullptr;             // [prime][dir] blocks of kR3TableWords words
+  std::map<uint64_t, dmi::PassTables> pass; // by N
   uint64_t* ws = nullptr;
   size_t ws_words = 0;
   int* d_status = nullptr;              // [0]: dmul_ex; [1 + i]: batch product i
@@ -104,10 +106,11 @@ struct dmul_ctx {
 namespace dmi {
 int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl);
 size_t workspace_words(const PlanDev& pl);
-int get_twiddles(dmul_ctx* ctx, int logN, int logR, TwiddleSet* tw);
+int get_twiddles(dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw);
 int ensure_workspace(dmul_ctx* ctx, size_t words);
 int ensure_rec_sync(dmul_ctx* ctx, size_t words);
-int row_iters_for(const dmul_ctx* ctx, int logN);
+int row_iters_for(const dmul_ctx* ctx, const PlanDev& pl);
+bool size_class(uint64_t N, int* rad3, int* e);
 int from_hip(hipError_t e);
 int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
                     uint64_t* out, unsigned flags, int* status, uint64_t* residues);

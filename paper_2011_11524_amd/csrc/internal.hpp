@@ -10,6 +10,9 @@ namespace dmi {
 
 constexpr int kMaxLogN = 26;       // two LDS passes of at most 2^13 points each
 constexpr int kMaxLogLen = 13;     // longest sub-transform held in one workgroup's LDS
+constexpr int kMaxLogC3 = 11;      // rows of 3 * 2^logC points: logC <= 11
+constexpr int kMaxLogR3 = 12;      // with C = 3M a column tile holds three columns of 2^logR points
+constexpr int kMinLogN3 = 4;       // lengths 3 * 2^e are used for e >= 4
 constexpr int kMinK = 13;          // p1*p2 < 10^(3k): three base-10^k parts per coefficient
 constexpr uint64_t kLimbBase = 10000000000000000000ULL;  // 10^19
 
@@ -24,26 +27,41 @@ struct DivTable {
 };
 
 // Everything a kernel needs about one product, passed by value.
+// The transform length is N = 2^logN (rad3 = 0) or 3 * 2^logN (rad3 = 1;
+// the primes' form c*3*2^n + 1 admits these lengths, Sections 4.5, 7.8).
+// It is laid out as R x C with R = 2^logR rows and C = 2^logC (rad3 = 0)
+// or 3 * 2^logC (rad3 = 1) columns.
 struct PlanDev {
   uint64_t na, nb;          // limbs of a and b (base 10^19)
   uint64_t n, m;            // base-10^k groups of a and b
-  uint64_t N;               // transform length, 2^logN
+  uint64_t N;               // transform length
   int k;                    // digits per group
-  int logN, logR, logC;     // N = R*C, R = 2^logR rows, C = 2^logC columns
+  int logN, logR, logC;     // logR + logC = logN
+  int rad3;                 // 1: N and C carry a factor 3
 };
+
+__host__ __device__ constexpr uint64_t row_len(int logC, int rad3) {
+  return (uint64_t)(rad3 ? 3 : 1) << logC;
+}
+// The inter-pass exponent e < N is split as e = e_hi * 2^lb + e_lo.
+__host__ __device__ constexpr int pass_split_bits(int logC, int rad3) { return logC + (rad3 ? 2 : 0); }
 
 // Device-side constant data for both primes, built once per context.
 struct Consts {
   Prime P[2];
   uint64_t r_tilde;         // R * (p1^-1 mod p2) mod p2 (Montgomery form for the CRT)
+  uint64_t kappa[2][2];     // [prime][0 forward, 1 inverse]: R * (w - w^2) / 2 mod p, w the
+                            // cube root of unity of that direction (radix-3 butterfly)
 };
 
 // Per transform-length tables for the inter-pass factor xi_N^(+-e), e < N,
-// split e = e_hi*C + e_lo (Montgomery form; the inverse low table also
-// carries the scale R^2 N^-1 of the linearity trick).
+// split e = e_hi*2^lb + e_lo with lb = pass_split_bits (Montgomery form; the
+// inverse low table also carries the scale R^2 N^-1 of the linearity trick).
 struct TwiddleSet {
   const uint64_t* len_fwd[2];   // [prime] -> base of per-length root tables (forward roots)
   const uint64_t* len_inv[2];   // [prime] -> same for inverse roots
+  const uint64_t* r3_fwd[2];    // [prime] -> base of the radix-3 row tables (forward)
+  const uint64_t* r3_inv[2];    // [prime] -> same, inverse
   const uint64_t* hi_fwd[2];
   const uint64_t* lo_fwd[2];
   const uint64_t* hi_inv[2];
@@ -53,6 +71,10 @@ struct TwiddleSet {
 // Offset of the table of w_L^i (i < L/2) for L = 2^l inside a per-prime
 // root-table block: tables for l = 1, 2, ... are stored back to back.
 __host__ __device__ constexpr size_t root_table_offset(int l) { return ((size_t)1 << (l - 1)) - 1; }
+// Offset of the table of w_C^i (i < 2M) for a row of C = 3M points, M = 2^l,
+// inside a per-prime radix-3 block: tables for l = 0, 1, ... back to back.
+__host__ __device__ constexpr size_t r3_table_offset(int l) { return 2 * (((size_t)1 << l) - 1); }
+constexpr size_t kR3TableWords = 2 * (((size_t)1 << (kMaxLogC3 + 1)) - 1);
 
 // Optional per-kernel timing: when set, a launch wrapper records an event on
 // the stream after each kernel it launches (phase ids below).
@@ -85,7 +107,7 @@ struct Work {
 
 // Grid shape shared by the products of a launch.
 struct Shape {
-  int logR, logC;
+  int logR, logC, rad3;
   int any_nonsquare;        // some product transforms two operands
   int row_iters;            // row groups per workgroup in the row pass
   uint32_t max_nblk;        // largest recovery grid among the products

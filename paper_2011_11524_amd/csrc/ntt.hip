@@ -1,14 +1,16 @@
 // Number-theoretic transforms for the two-pass ("six-step" without its
 // transpositions) layout of Section 7, on gfx950.
 //
-// A length-N transform, N = R*C (R = 2^logR rows, C = 2^logC columns,
-// row-major, Section 7.9's split R = 2^floor(logN/2)), runs as
+// A length-N transform, N = R*C (R = 2^logR rows, C = 2^logC or 3*2^logC
+// columns, row-major, Section 7.9's split R = 2^floor(logN/2)), runs as
 //   forward:  pass A  R-point DIF on every column, then x *= xi_N^(k1*n2)
 //             pass B  C-point DIF on every row
 //   inverse:  pass B  pointwise REDC(X, Y), C-point DIT on every row
 //             pass A  x *= xi_N^(-k1*n2) * R^2 N^-1, R-point DIT on every column
 // DIF leaves its outputs in bit-reversed order and DIT consumes that order,
 // so no bit reversal and no transposition is ever done (Sections 5.4, 7.4);
+// a row of C = 3M points runs a length-3 DFT across its thirds first (DIF)
+// or last (DIT) around three M-point transforms (Section 7.8);
 // the pointwise product does not care about the order (eq.
 // cdot_permutation_invariance).  Row k1 of the forward output is held at
 // row position i = rev(k1), which is why the inter-pass factor uses rev(i).
@@ -202,12 +204,32 @@ __device__ __forceinline__ uint32_t bitrev(uint32_t i, int bits) {
   return bits == 0 ? 0u : (__brev(i) >> (32 - bits));
 }
 
-// Inter-pass factor xi_N^(+-e) (times the inverse scale), e = e_hi*C + e_lo.
+// Inter-pass factor xi_N^(+-e) (times the inverse scale), e = e_hi*2^lb + e_lo.
 __device__ __forceinline__ uint64_t pass_factor(const uint64_t* __restrict__ hi,
                                                 const uint64_t* __restrict__ lo, uint64_t e,
-                                                int logC, const Prime& P) {
-  const uint64_t C1 = ((uint64_t)1 << logC) - 1;
-  return mont_mul(hi[e >> logC], lo[e & C1], P);
+                                                int lb, const Prime& P) {
+  const uint64_t L1 = ((uint64_t)1 << lb) - 1;
+  return mont_mul(hi[e >> lb], lo[e & L1], P);
+}
+
+// x / 2 mod p for x < p (p odd): x >> 1, or (x + p) / 2 for odd x.
+__device__ __forceinline__ uint64_t half_mod(uint64_t x, const Prime& P) {
+  return (x >> 1) + ((x & 1) ? (P.p >> 1) + 1 : 0);
+}
+
+// Length-3 DFT of (a, b, c) with the cube root of unity w of the direction
+// (Section 7.8): y0 = a + b + c, y1 = a + w b + w^2 c, y2 = a + w^2 b + w c.
+// Since 1 + w + w^2 = 0, y1 = m + v and y2 = m - v with m = a - (b + c)/2
+// and v = kappa (b - c), kappa = (w - w^2)/2 held in Montgomery form: one
+// REDC per three outputs.
+__device__ __forceinline__ void dft3(uint64_t& a, uint64_t& b, uint64_t& c, uint64_t kappa,
+                                     const Prime& P) {
+  const uint64_t bc = add_mod(b, c, P);
+  const uint64_t m = sub_mod(a, half_mod(bc, P), P);
+  const uint64_t v = mont_mul(sub_lazy(b, c, P), kappa, P);
+  a = add_mod(a, bc, P);
+  b = add_mod(m, v, P);
+  c = sub_mod(m, v, P);
 }
 
 // The product a kernel works on: the launch's single descriptor, or entry
@@ -218,20 +240,42 @@ __device__ __forceinline__ ProdDesc load_desc(const Work& w) {
 }
 
 // ---------------------------------------------------------------------------
-// Pass A, forward: split + column DIF + inter-pass factor.
-// grid.x = C / T column tiles, grid.y = operand, grid.z = product.  The
-// digit groups of the tile are split once, kept in registers, and
-// transformed for each prime in turn (the groups are below 10^k < p, the
-// same residues for both primes).  The root tables of length R for both
-// primes and the power-of-ten table are staged in LDS.
+// Pass A tiles.  A tile is T column slots of the R x C matrix.  For C = 2^c
+// they are the T adjacent columns j0 + l.  For C = 3M (R3) they are TS = T/3
+// column triples: slot s*TS + l holds column s*M + q0 + l (s < 3), so the
+// tile holds, for each row, the three points q, q+M, q+2M that the
+// length-3 step of the row transform combines (Section 7.8).
 // ---------------------------------------------------------------------------
-template <int LOGR, int LOGE, int T>
+template <int T, bool R3>
+struct Tile {
+  static constexpr int TS = R3 ? T / 3 : T;
+  uint64_t first;     // j0 (C = 2^c) or q0 (C = 3M)
+  uint64_t M, C;
+  __device__ Tile(uint64_t blk, int logC, int rad3)
+      : first(blk * TS), M((uint64_t)1 << logC), C(row_len(logC, rad3)) {}
+  __device__ uint64_t column(int slot) const {
+    return R3 ? (uint64_t)(slot / TS) * M + first + slot % TS : first + slot;
+  }
+  __device__ bool valid(int slot) const { return R3 ? first + slot % TS < M : first + slot < C; }
+};
+
+// ---------------------------------------------------------------------------
+// Pass A, forward: split + column DIF + inter-pass factor (+ for C = 3M the
+// length-3 DFT across the thirds of each row and the factor w_C^(s*q)).
+// grid.x = column tiles, grid.y = operand, grid.z = product.  The digit
+// groups of the tile are split once, kept in registers, and transformed for
+// each prime in turn (the groups are below 10^k < p, the same residues for
+// both primes).  The root tables of length R for both primes and the
+// power-of-ten table are staged in LDS.
+// ---------------------------------------------------------------------------
+template <int LOGR, int LOGE, int T, bool R3>
 __global__ void __launch_bounds__((T * Geometry<LOGR, LOGE>::NT))
 k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) {
   using G = Geometry<LOGR, LOGE>;
   constexpr int R = G::L;
   constexpr int NTH = T * G::NT;                 // threads
   constexpr int PER = (R * T + NTH - 1) / NTH;   // tile points per thread
+  constexpr int TS = Tile<T, R3>::TS;
   extern __shared__ uint64_t lds[];
   uint64_t* troots = lds + T * G::STRIDE;        // [prime][R/2]
   const ProdDesc d = load_desc(w);
@@ -241,9 +285,9 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
   const uint64_t nl = op ? d.pl.nb : d.pl.na;
   const uint64_t ng = op ? d.pl.m : d.pl.n;
   const uint64_t N = d.pl.N;
-  const int logC = d.pl.logC;
-  const uint64_t C = (uint64_t)1 << logC;
-  const uint64_t j0 = (uint64_t)blockIdx.x * T;
+  const Tile<T, R3> tile(blockIdx.x, d.pl.logC, d.pl.rad3);
+  const uint64_t C = tile.C;
+  const int lb = pass_split_bits(d.pl.logC, d.pl.rad3);
   __shared__ DivTable sdt;
   for (unsigned i = threadIdx.x; i < sizeof(DivTable) / 4; i += blockDim.x)
     reinterpret_cast<uint32_t*>(&sdt)[i] = reinterpret_cast<const uint32_t*>(dt_g)[i];
@@ -255,9 +299,10 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
   }
   __syncthreads();
   for (int q = threadIdx.x; q < R * T; q += NTH) {
-    const int row = q / T, col = q % T;
-    lds[col * G::STRIDE + lds_pos<LOGE>(row)] =
-        j0 + col < C ? split_group(src, nl, ng, (uint64_t)row * C + j0 + col, d.pl.k, dt, d.status) : 0;
+    const int row = q / T, sl = q % T;
+    lds[sl * G::STRIDE + lds_pos<LOGE>(row)] =
+        tile.valid(sl) ? split_group(src, nl, ng, (uint64_t)row * C + tile.column(sl), d.pl.k, dt, d.status)
+                       : 0;
   }
   __syncthreads();
   uint64_t v[PER];   // the split tile, kept for the second prime
@@ -280,13 +325,39 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
       __syncthreads();
     }
     lds_transform<LOGR, LOGE, false>(lds + col * G::STRIDE, troots + pi * (R / 2), P, t, true);
-    for (int q = threadIdx.x; q < R * T; q += NTH) {
-      const int row = q / T, c = q % T;
-      if (j0 + c >= C) continue;
-      const uint64_t e = (uint64_t)bitrev(row, LOGR) * (j0 + c);
-      uint64_t x = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
-      x = mont_mul(x, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], e, logC, P), P);
-      dst[(uint64_t)row * C + j0 + c] = x;
+    if constexpr (!R3) {
+      for (int q = threadIdx.x; q < R * T; q += NTH) {
+        const int row = q / T, c = q % T;
+        if (!tile.valid(c)) continue;
+        const uint64_t j = tile.column(c);
+        const uint64_t e = (uint64_t)bitrev(row, LOGR) * j;
+        uint64_t x = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
+        x = mont_mul(x, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], e, lb, P), P);
+        dst[(uint64_t)row * C + j] = x;
+      }
+    } else {
+      const uint64_t* w3 = tw.r3_fwd[pi] + r3_table_offset(d.pl.logC);
+      const uint64_t M = tile.M;
+      for (int q = threadIdx.x; q < R * TS; q += NTH) {
+        const int row = q / TS, c = q % TS;
+        if (!tile.valid(c)) continue;
+        const uint64_t qc = tile.first + c;
+        const uint64_t rv = bitrev(row, LOGR);
+        const int o = lds_pos<LOGE>(row);
+        uint64_t x0 = lds[c * G::STRIDE + o];
+        uint64_t x1 = lds[(TS + c) * G::STRIDE + o];
+        uint64_t x2 = lds[(2 * TS + c) * G::STRIDE + o];
+        x0 = mont_mul(x0, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], rv * qc, lb, P), P);
+        x1 = mont_mul(x1, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], rv * (M + qc), lb, P), P);
+        x2 = mont_mul(x2, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], rv * (2 * M + qc), lb, P), P);
+        dft3(x0, x1, x2, cs.kappa[pi][0], P);
+        x1 = mont_mul(x1, w3[qc], P);
+        x2 = mont_mul(x2, w3[2 * qc], P);
+        uint64_t* rowp = dst + (uint64_t)row * C + qc;
+        rowp[0] = x0;
+        rowp[M] = x1;
+        rowp[2 * M] = x2;
+      }
     }
     __syncthreads();
   }
@@ -295,7 +366,9 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
 // ---------------------------------------------------------------------------
 // Pass B: row transforms.  Forward: DIF in place on every row of every
 // (operand, prime) buffer.  Inverse: pointwise REDC(X, Y) then DIT, written
-// over X.
+// over X.  With C = 3M the rows are the 3R sub-rows of M points (the
+// length-3 step across each row's thirds is done by the column passes), so
+// a "row" here is always 2^LOGC contiguous points.
 //
 // grid.y selects the buffer (forward: prime + 2*operand; inverse: prime),
 // grid.z the product; the workgroups along x loop over groups of RPW rows
@@ -319,7 +392,7 @@ k_rows(Work w, Consts cs, TwiddleSet tw) {
   const Prime P = cs.P[pi];
   uint64_t* X = d.ws + (size_t)y * d.pl.N;                       // inverse: y = prime
   const uint64_t* Y = d.ws + (size_t)(d.square ? pi : 2 + pi) * d.pl.N;
-  const uint64_t R = (uint64_t)1 << d.pl.logR;
+  const uint64_t R = (uint64_t)(d.pl.rad3 ? 3 : 1) << d.pl.logR;  // rows of C points
   const uint32_t groups = (uint32_t)((R + RPW - 1) / RPW);
   const int r = threadIdx.x / NT, t = threadIdx.x % NT;
   uint64_t* row_lds = lds + r * G::STRIDE;
@@ -379,43 +452,72 @@ k_rows(Work w, Consts cs, TwiddleSet tw) {
 }
 
 // ---------------------------------------------------------------------------
-// Pass A, inverse: inter-pass factor with scale, then column DIT; the
-// result is the residue of each convolution coefficient, in natural order.
+// Pass A, inverse: (for C = 3M first the factor w_C^(-s*q) and the inverse
+// length-3 DFT across the thirds of each row, completing the row
+// transform), inter-pass factor with scale, then column DIT; the result is
+// the residue of each convolution coefficient, in natural order.
 // grid.x = column tiles, grid.y = prime, grid.z = product.
 // ---------------------------------------------------------------------------
-template <int LOGR, int LOGE, int T>
+template <int LOGR, int LOGE, int T, bool R3>
 __global__ void __launch_bounds__((T * Geometry<LOGR, LOGE>::NT))
 k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   using G = Geometry<LOGR, LOGE>;
+  constexpr int TS = Tile<T, R3>::TS;
   extern __shared__ uint64_t lds[];
   uint64_t* troots = lds + T * G::STRIDE;
   const ProdDesc d = load_desc(w);
   const int pi = blockIdx.y;
   const Prime P = cs.P[pi];
   uint64_t* X = d.ws + (size_t)pi * d.pl.N;
-  const int logC = d.pl.logC;
-  const uint64_t C = (uint64_t)1 << logC;
-  const uint64_t j0 = (uint64_t)blockIdx.x * T;
+  const Tile<T, R3> tile(blockIdx.x, d.pl.logC, d.pl.rad3);
+  const uint64_t C = tile.C;
+  const int lb = pass_split_bits(d.pl.logC, d.pl.rad3);
   constexpr int R = G::L;
 
   for (int i = threadIdx.x; i < R / 2; i += blockDim.x)
     troots[i] = tw.len_inv[pi][root_table_offset(LOGR) + i];
-  for (int q = threadIdx.x; q < R * T; q += blockDim.x) {
-    const int row = q / T, c = q % T;
-    uint64_t v = 0;
-    if (j0 + c < C) {
-      const uint64_t e = (uint64_t)bitrev(row, LOGR) * (j0 + c);
-      v = X[(uint64_t)row * C + j0 + c];
-      v = mont_mul(v, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], e, logC, P), P);
+  if constexpr (!R3) {
+    for (int q = threadIdx.x; q < R * T; q += blockDim.x) {
+      const int row = q / T, c = q % T;
+      uint64_t v = 0;
+      if (tile.valid(c)) {
+        const uint64_t j = tile.column(c);
+        const uint64_t e = (uint64_t)bitrev(row, LOGR) * j;
+        v = X[(uint64_t)row * C + j];
+        v = mont_mul(v, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], e, lb, P), P);
+      }
+      lds[c * G::STRIDE + lds_pos<LOGE>(row)] = v;
     }
-    lds[c * G::STRIDE + lds_pos<LOGE>(row)] = v;
+  } else {
+    const uint64_t* w3 = tw.r3_inv[pi] + r3_table_offset(d.pl.logC);
+    const uint64_t M = tile.M;
+    for (int q = threadIdx.x; q < R * TS; q += blockDim.x) {
+      const int row = q / TS, c = q % TS;
+      const int o = lds_pos<LOGE>(row);
+      uint64_t x0 = 0, x1 = 0, x2 = 0;
+      if (tile.valid(c)) {
+        const uint64_t qc = tile.first + c;
+        const uint64_t* rowp = X + (uint64_t)row * C + qc;
+        x0 = rowp[0];
+        x1 = mont_mul(rowp[M], w3[qc], P);
+        x2 = mont_mul(rowp[2 * M], w3[2 * qc], P);
+        dft3(x0, x1, x2, cs.kappa[pi][1], P);
+        const uint64_t rv = bitrev(row, LOGR);
+        x0 = mont_mul(x0, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], rv * qc, lb, P), P);
+        x1 = mont_mul(x1, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], rv * (M + qc), lb, P), P);
+        x2 = mont_mul(x2, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], rv * (2 * M + qc), lb, P), P);
+      }
+      lds[c * G::STRIDE + o] = x0;
+      lds[(TS + c) * G::STRIDE + o] = x1;
+      lds[(2 * TS + c) * G::STRIDE + o] = x2;
+    }
   }
   __syncthreads();
   const int col = threadIdx.x / G::NT, t = threadIdx.x % G::NT;
   lds_transform<LOGR, LOGE, true>(lds + col * G::STRIDE, troots, P, t, true);
   for (int q = threadIdx.x; q < R * T; q += blockDim.x) {
     const int row = q / T, c = q % T;
-    if (j0 + c < C) X[(uint64_t)row * C + j0 + c] = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
+    if (tile.valid(c)) X[(uint64_t)row * C + tile.column(c)] = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
   }
 }
 
@@ -423,16 +525,35 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
 // Launch configuration and dispatch over the compile-time lengths.
 // ---------------------------------------------------------------------------
 constexpr int loge_for(int logl) { return logl < 4 ? logl : 4; }
-// Columns per tile for a target workgroup size (at most 64 columns).  The
-// forward column pass keeps the split tile in registers for its second
-// prime, so it runs smaller workgroups (256 threads) to fit three per CU;
-// the inverse one runs 512.
-constexpr int cols_for_threads(int logl, int threads) {
-  return (threads >> (logl - loge_for(logl))) < 1 ? 1
-         : ((threads >> (logl - loge_for(logl))) > 64 ? 64 : (threads >> (logl - loge_for(logl))));
+// LDS words a workgroup may use (160 KB per CU, less the static tables).
+constexpr int kLdsWords = (160 * 1024 - 1024) / 8;
+constexpr int col_stride(int logl) { return (1 << logl) + ((1 << logl) >> loge_for(logl)) + 1; }
+// Column tiles: as many columns as fit a target workgroup size (at most 64)
+// and the LDS next to `extra` words of tables.  Wide tiles matter: every
+// global access of a column pass is a run of T contiguous words of one row,
+// and runs below a 128-byte line waste HBM transactions.
+constexpr int cols_for(int logl, int threads, int extra) {
+  int t = 1;
+  while (t < 64 && 2 * t * (1 << (logl - loge_for(logl))) <= threads &&
+         2 * t * col_stride(logl) + extra <= kLdsWords)
+    t *= 2;
+  return t;
 }
-constexpr int cols_per_tile(int logl) { return cols_for_threads(logl, 512); }
-constexpr int fwd_cols_per_tile(int logl) { return cols_for_threads(logl, 256); }
+// Column triples per tile (C = 3M): the largest power of two, 1..16, within
+// the thread target and the LDS.
+constexpr int triples_for(int logl, int threads, int extra) {
+  int t = 1;
+  while (t < 16 && 2 * t * 3 * (1 << (logl - loge_for(logl))) <= threads &&
+         2 * t * 3 * col_stride(logl) + extra <= kLdsWords)
+    t *= 2;
+  return t;
+}
+// Forward tiles (whose kernel also keeps the split tile in registers) aim at
+// 512 threads, 768 with column triples; inverse tiles at 1024.
+constexpr int fwd_cols_per_tile(int logl) { return cols_for(logl, 512, 1 << logl); }
+constexpr int cols_per_tile(int logl) { return cols_for(logl, 1024, (1 << logl) / 2); }
+constexpr int fwd_triples_per_tile(int logl) { return triples_for(logl, 768, 1 << logl); }
+constexpr int triples_per_tile(int logl) { return triples_for(logl, 1024, (1 << logl) / 2); }
 constexpr int rows_per_wg(int logl) {
   return (256 >> (logl - loge_for(logl))) < 1 ? 1 : (256 >> (logl - loge_for(logl)));
 }
@@ -445,31 +566,44 @@ static hipError_t prepare(K kernel, size_t lds_bytes) {
   return hipSuccess;
 }
 
-template <int LOGR>
-static hipError_t fwd_cols_l(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
-                             const DivTable* dt, hipStream_t st) {
-  constexpr int LOGE = loge_for(LOGR), T = fwd_cols_per_tile(LOGR);
+template <int LOGR, bool R3>
+static hipError_t fwd_cols_launch(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                                  const DivTable* dt, hipStream_t st) {
+  constexpr int LOGE = loge_for(LOGR);
+  constexpr int T = R3 ? 3 * fwd_triples_per_tile(LOGR) : fwd_cols_per_tile(LOGR);
+  constexpr int TS = R3 ? T / 3 : T;
   using G = Geometry<LOGR, LOGE>;
   const size_t lds = ((size_t)T * G::STRIDE + (size_t)G::L) * sizeof(uint64_t);
-  auto kern = k_fwd_cols<LOGR, LOGE, T>;
+  auto kern = k_fwd_cols<LOGR, LOGE, T, R3>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
-  const uint64_t C = (uint64_t)1 << sh.logC;
-  dim3 grid((unsigned)((C + T - 1) / T), sh.any_nonsquare ? 2 : 1, w.count);
+  const uint64_t span = R3 ? (uint64_t)1 << sh.logC : row_len(sh.logC, 0);   // tiles cover M or C
+  dim3 grid((unsigned)((span + TS - 1) / TS), sh.any_nonsquare ? 2 : 1, w.count);
   hipLaunchKernelGGL(kern, grid, dim3(T * G::NT), lds, st, w, cs, tw, dt);
   return hipGetLastError();
 }
 
-template <int LOGC, bool INV, bool TWL>
-static hipError_t rows_launch(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
-                              hipStream_t st) {
+template <int LOGR>
+static hipError_t fwd_cols_l(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                             const DivTable* dt, hipStream_t st) {
+  if constexpr (LOGR <= kMaxLogR3) {
+    if (sh.rad3) return fwd_cols_launch<LOGR, true>(w, sh, cs, tw, dt, st);
+  } else {
+    if (sh.rad3) return hipErrorInvalidValue;
+  }
+  return fwd_cols_launch<LOGR, false>(w, sh, cs, tw, dt, st);
+}
+
+template <int LOGC, bool INV>
+static hipError_t rows_l(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                         hipStream_t st) {
   constexpr int LOGE = loge_for(LOGC), RPW = rows_per_wg(LOGC);
   using G = Geometry<LOGC, LOGE>;
-  const size_t lds = ((size_t)RPW * G::STRIDE + (TWL ? (size_t)G::L / 2 : 0)) * sizeof(uint64_t);
-  auto kern = k_rows<LOGC, LOGE, RPW, INV, TWL>;
+  const size_t lds = ((size_t)RPW * G::STRIDE + (size_t)G::L / 2) * sizeof(uint64_t);
+  auto kern = k_rows<LOGC, LOGE, RPW, INV, true>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
-  const uint64_t R = (uint64_t)1 << sh.logR;
+  const uint64_t R = (uint64_t)(sh.rad3 ? 3 : 1) << sh.logR;    // rows of 2^logC points
   const uint64_t groups = (R + RPW - 1) / RPW;
   const int iters = sh.row_iters > 0 ? sh.row_iters : 1;
   const unsigned gx = (unsigned)((groups + iters - 1) / iters);
@@ -478,25 +612,32 @@ static hipError_t rows_launch(const Work& w, const Shape& sh, const Consts& cs, 
   return hipGetLastError();
 }
 
-template <int LOGC, bool INV>
-static hipError_t rows_l(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
-                         hipStream_t st) {
-  return rows_launch<LOGC, INV, true>(w, sh, cs, tw, st);
+template <int LOGR, bool R3>
+static hipError_t inv_cols_launch(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                                  hipStream_t st) {
+  constexpr int LOGE = loge_for(LOGR);
+  constexpr int T = R3 ? 3 * triples_per_tile(LOGR) : cols_per_tile(LOGR);
+  constexpr int TS = R3 ? T / 3 : T;
+  using G = Geometry<LOGR, LOGE>;
+  const size_t lds = ((size_t)T * G::STRIDE + (size_t)G::L / 2) * sizeof(uint64_t);
+  auto kern = k_inv_cols<LOGR, LOGE, T, R3>;
+  hipError_t e = prepare(kern, lds);
+  if (e != hipSuccess) return e;
+  const uint64_t span = R3 ? (uint64_t)1 << sh.logC : row_len(sh.logC, 0);
+  dim3 grid((unsigned)((span + TS - 1) / TS), 2, w.count);
+  hipLaunchKernelGGL(kern, grid, dim3(T * G::NT), lds, st, w, cs, tw);
+  return hipGetLastError();
 }
 
 template <int LOGR>
 static hipError_t inv_cols_l(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                              hipStream_t st) {
-  constexpr int LOGE = loge_for(LOGR), T = cols_per_tile(LOGR);
-  using G = Geometry<LOGR, LOGE>;
-  const size_t lds = ((size_t)T * G::STRIDE + (size_t)G::L / 2) * sizeof(uint64_t);
-  auto kern = k_inv_cols<LOGR, LOGE, T>;
-  hipError_t e = prepare(kern, lds);
-  if (e != hipSuccess) return e;
-  const uint64_t C = (uint64_t)1 << sh.logC;
-  dim3 grid((unsigned)((C + T - 1) / T), 2, w.count);
-  hipLaunchKernelGGL(kern, grid, dim3(T * G::NT), lds, st, w, cs, tw);
-  return hipGetLastError();
+  if constexpr (LOGR <= kMaxLogR3) {
+    if (sh.rad3) return inv_cols_launch<LOGR, true>(w, sh, cs, tw, st);
+  } else {
+    if (sh.rad3) return hipErrorInvalidValue;
+  }
+  return inv_cols_launch<LOGR, false>(w, sh, cs, tw, st);
 }
 
 #define DMUL_LEN_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13)

@@ -1,11 +1,13 @@
 """Size-class autotuner for batched products.
 
-For every transform length 2^L in a range, build a batch of products whose
-plans have that length (operands of random digits), time the batch with each
+For every transform length N (2^L or 3 * 2^(L-2), the size classes of the
+planner) with 2^min <= N <= 2^max, build a batch of products whose plans
+have that length (operands of random digits), time the batch with each
 candidate launch parameter, and write the fastest choice per class to
-dmul_tune.txt beside the library (read by every new context).  The tuned
-parameter is the number of row groups each workgroup of the row pass loops
-over (1 = one group per workgroup, more = fewer, longer-lived workgroups).
+dmul_tune.txt beside the library (read by every new context): lines
+"N row_iters".  The tuned parameter is the number of row groups each
+workgroup of the row pass loops over (1 = one group per workgroup, more =
+fewer, longer-lived workgroups).
 
     python -m paper_2011_11524_amd.tune [--min 7] [--max 21] [--out PATH]
 """
@@ -21,15 +23,22 @@ import numpy as np
 CANDIDATES = (1, 2, 4, 8)
 
 
-def limbs_for_class(L: int) -> int:
-    """Operand limbs for a balanced product whose transform length is 2^L."""
+def size_classes(lo_log: int, hi_log: int) -> list:
+    """Transform lengths 2^L and 3 * 2^e within [2^lo_log, 2^hi_log], sorted."""
+    out = {1 << L for L in range(lo_log, hi_log + 1)}
+    out |= {3 << e for e in range(4, hi_log) if (1 << lo_log) <= (3 << e) <= (1 << hi_log)}
+    return sorted(out)
+
+
+def limbs_for_class(N: int) -> int:
+    """Operand limbs of the longest balanced product whose transform length
+    is at most N (the planner's length grows with the operands)."""
     import paper_2011_11524_amd as dm
     lo, hi = 1, 1 << 24
-    # largest na with plan(na, na).log2_n <= L
     while lo < hi:
         mid = (lo + hi + 1) // 2
         try:
-            ok = dm.plan(mid, mid).log2_n <= L
+            ok = dm.plan(mid, mid).N <= N
         except dm.DmulError:
             ok = False
         lo, hi = (mid, hi) if ok else (lo, mid - 1)
@@ -63,11 +72,11 @@ def main(argv=None) -> int:
     rng = np.random.default_rng(6006)
     ctx = dm.Context(0)
     rows = []
-    for L in range(args.min, args.max + 1):
-        nl = limbs_for_class(L)
-        if dm.plan(nl, nl).log2_n != L:
+    for N in size_classes(args.min, args.max):
+        nl = limbs_for_class(N)
+        if dm.plan(nl, nl).N != N:
             continue
-        count = int(max(1, min(4096, args.work // (1 << L))))
+        count = int(max(1, min(4096, args.work // N)))
         pairs, outs = [], []
         for _ in range(count):
             a = rng.integers(0, 10 ** 19, size=nl, dtype=np.uint64)
@@ -77,20 +86,20 @@ def main(argv=None) -> int:
         best = None
         times = {}
         for it in CANDIDATES:
-            ctx.tune(L, it)
+            ctx.tune(N, it)
             t = time_batch(ctx, pairs, outs, args.reps)
             times[it] = t
             if best is None or t < times[best]:
                 best = it
-        ctx.tune(L, 0)
-        rows.append((L, best, times))
-        print(f"log2N={L:2d} products={count:5d} " +
+        ctx.tune(N, 0)
+        rows.append((N, best, times))
+        print(f"N={N:8d} products={count:5d} " +
               " ".join(f"iters{k}={v * 1e3:.3f}ms" for k, v in times.items()) + f" -> {best}", flush=True)
     ctx.close()
     with open(args.out, "w") as f:
-        f.write("# size-class table written by paper_2011_11524_amd/tune.py: log2N row_iters\n")
-        for L, best, times in rows:
-            f.write(f"{L} {best}\n")
+        f.write("# size-class table written by paper_2011_11524_amd/tune.py: N row_iters\n")
+        for N, best, times in rows:
+            f.write(f"{N} {best}\n")
     print(f"wrote {args.out}")
     return 0
 

@@ -38,22 +38,44 @@ def test_strerror():
     assert "10^19" in dm.strerror(dm.DMUL_EDIGIT)
 
 
-@pytest.mark.parametrize("na,nb", [(1, 1), (2, 3), (80, 80), (81, 81), (5264, 5264), (526316, 526316),
-                                   (2105264, 1052632), (10**6, 3), (3, 10**6), (12345, 67890)])
-def test_plan_matches_oracle_rule(na, nb):
-    p = dm.plan(na, nb)
+def _lengths(need, pow2):
+    """Transform lengths the planner may pick for `need` coefficients, in
+    increasing order: 2^e (2 <= e <= 26) and, unless pow2, 3*2^e
+    (4 <= e <= 23), each with its R x C layout (log2 R, log2 C)."""
+    out = []
+    for e in range(2, 27):
+        out.append((1 << e, 1, e, e // 2))
+    if not pow2:
+        for e in range(4, 24):
+            out.append((3 << e, 3, e, max(e // 2, e - 11)))
+    return sorted(o for o in out if o[0] >= need)
+
+
+SIZES = [(1, 1), (2, 3), (80, 80), (81, 81), (5264, 5264), (526316, 526316), (2105264, 1052632),
+         (10**6, 3), (3, 10**6), (12345, 67890), (7, 9), (40, 41), (300, 200)]
+
+
+@pytest.mark.parametrize("pow2", [False, True])
+@pytest.mark.parametrize("na,nb", SIZES)
+def test_plan_matches_oracle_rule(na, nb, pow2):
+    p = dm.plan(na, nb, pow2=pow2)
     assert p.k == oracle.choose_k(na, nb)
     n = -(-19 * na // p.k)
     m = -(-19 * nb // p.k)
     assert (p.groups_a, p.groups_b) == (n, m)
-    assert 2 ** (p.log2_n - 1) < n + m <= 2 ** p.log2_n or (p.log2_n == 2 and n + m <= 4)
-    assert p.log2_rows == p.log2_n // 2 and p.log2_rows + p.log2_cols == p.log2_n
-    assert p.workspace_bytes == 32 * p.N == dm.workspace_bytes(na, nb)
+    N, factor, e, log_r = _lengths(n + m, pow2)[0]
+    assert (p.N, p.factor, p.log2_n, p.log2_rows) == (N, factor, e, log_r)
+    assert p.log2_rows + p.log2_cols == p.log2_n
+    assert p.workspace_bytes == 32 * p.N == (dm.workspace_bytes(na, nb) if not pow2 else 32 * p.N)
 
 
 def test_plan_forced_k_and_ranges():
-    assert dm.plan(2105264, 1052632, force_k=14).log2_n == 23
-    assert dm.plan(2105264, 1052632).log2_n == 22
+    # C3 at k = 14: 4,285,715 coefficients fit 3*2^21 (2048 rows of 3*1024)
+    p = dm.plan(2105264, 1052632, force_k=14)
+    assert (p.N, p.factor, p.log2_rows, p.log2_cols) == (3 << 21, 3, 10, 11)
+    assert dm.plan(2105264, 1052632, force_k=14, pow2=True).log2_n == 23
+    assert dm.plan(2105264, 1052632).N == 1 << 22       # 4,000,001 <= 2^22 < 3*2^21
+    assert dm.plan(526316, 526316).N == 3 << 19          # C2: 1,250,000 -> 1,572,864
     with pytest.raises(dm.DmulError) as e:
         dm.plan(81, 81, force_k=18)         # 86 groups of 18 digits break the bound
     assert e.value.code == dm.DMUL_ERANGE
@@ -63,4 +85,9 @@ def test_plan_forced_k_and_ranges():
     with pytest.raises(dm.DmulError) as e:
         dm.plan(2 ** 30, 2 ** 30)           # beyond two LDS passes
     assert e.value.code == dm.DMUL_ERANGE
+    # the longest 3*2^e length: 3*2^23 = 2^12 rows of 3*2^11; beyond it 2^25
+    na = (3 << 23) * 15 // 19 // 2
+    p = dm.plan(na, na)
+    assert (p.N, p.log2_rows, p.log2_cols) == (3 << 23, 12, 11)
+    assert dm.plan(na + 1000, na + 1000).N == 1 << 25
     assert dm.workspace_bytes(0, 5) == 0

@@ -45,23 +45,35 @@ def _rand_limbs(rng, n):
     return np.array([rng.randrange(10 ** 19) for _ in range(n)], dtype=np.uint64)
 
 
-def _gpu_mul(dm, ctx, a, b, force_k=0):
+def _gpu_mul(dm, ctx, a, b, force_k=0, pow2=False):
     da = dm.to_device(a)
     db = da if b is a else dm.to_device(b)
-    return dm.to_host(ctx.mul(da, db, force_k=force_k))
+    return dm.to_host(ctx.mul(da, db, force_k=force_k, pow2=pow2))
+
+
+_ORACLE_CACHE = {}
+
+
+def _oracle_mul(key, a, b, force_k=0):
+    """oracle.mul_ntt, memoised per test case so both length families share it."""
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE.clear()
+        _ORACLE_CACHE[key] = oracle.mul_ntt(a, b, force_k=force_k)
+    return _ORACLE_CACHE[key]
 
 
 SMALL = [(1, 1), (1, 2), (2, 1), (3, 5), (7, 7), (17, 31), (64, 3), (80, 80), (81, 81), (100, 1),
          (1, 100), (255, 257), (1000, 1000), (1000, 37), (2049, 2047), (4000, 300), (5264, 5264)]
 
 
+@pytest.mark.parametrize("pow2", [False, True])
 @pytest.mark.parametrize("na,nb", SMALL)
-def test_random_products_match_oracle(dm, ctx, na, nb):
-    _note(f"random {na}x{nb}")
+def test_random_products_match_oracle(dm, ctx, na, nb, pow2):
+    _note(f"random {na}x{nb} pow2={pow2}")
     rng = random.Random(na * 7919 + nb)
     a = _rand_limbs(rng, na)
     b = _rand_limbs(rng, nb)
-    got = _gpu_mul(dm, ctx, a, b)
+    got = _gpu_mul(dm, ctx, a, b, pow2=pow2)
     np.testing.assert_array_equal(got, oracle.mul_ntt(a, b))
     if na * nb <= 10 ** 6:
         np.testing.assert_array_equal(got, oracle.schoolbook(a, b))
@@ -91,30 +103,107 @@ def _groups(x_limbs, k, count):
     return out
 
 
-@pytest.mark.parametrize("na,nb", [(1, 1), (3, 4), (40, 40), (100, 60), (400, 333)])
-def test_convolution_residues(dm, ctx, na, nb):
+@pytest.mark.parametrize("pow2", [False, True])
+@pytest.mark.parametrize("na,nb", [(1, 1), (3, 4), (40, 40), (100, 60), (400, 333), (37, 500)])
+def test_convolution_residues(dm, ctx, na, nb, pow2):
     """The transform step alone: the device residues equal the cyclic
-    convolution of the digit groups mod each prime, computed with the
-    oracle's pinned transform (convolution theorem)."""
-    _note(f"residues {na}x{nb}")
+    convolution of the digit groups mod each prime.  The expected values
+    come from the oracle's pinned radix-2 transform (convolution theorem) at
+    the power-of-two length L >= n + m; with N >= n + m no coefficient
+    wraps, so the length-N cyclic convolution is that result padded with
+    zeros (for N = 3*2^e as well)."""
+    _note(f"residues {na}x{nb} pow2={pow2}")
     rng = random.Random(na + 1000 * nb)
     a = _rand_limbs(rng, na)
     b = _rand_limbs(rng, nb)
-    pl = dm.plan(na, nb)
+    pl = dm.plan(na, nb, pow2=pow2)
     N = pl.N
-    x = _groups(a, pl.k, pl.groups_a) + [0] * (N - pl.groups_a)
-    y = _groups(b, pl.k, pl.groups_b) + [0] * (N - pl.groups_b)
-    r1, r2 = ctx.residues(dm.to_device(a), dm.to_device(b))
+    n, m = pl.groups_a, pl.groups_b
+    L = 1
+    while L < n + m:
+        L *= 2
+    x = _groups(a, pl.k, n) + [0] * (L - n)
+    y = _groups(b, pl.k, m) + [0] * (L - m)
+    r1, r2 = ctx.residues(dm.to_device(a), dm.to_device(b), pow2=pow2)
     for p, got in ((P1, dm.to_host(r1)), (P2, dm.to_host(r2))):
         g = oracle.generator(p)
-        xi = pow(g, (p - 1) // N, p)
+        xi = pow(g, (p - 1) // L, p)
         fx = oracle.transform(x, p, xi)
         fy = oracle.transform(y, p, xi)
         prod = [int(u) * int(v) % p for u, v in zip(fx, fy)]
         back = oracle.transform(prod, p, pow(xi, p - 2, p))
-        ninv = pow(N, p - 2, p)
-        want = np.array([int(v) * ninv % p for v in back], dtype=np.uint64)
-        np.testing.assert_array_equal(got, want)
+        linv = pow(L, p - 2, p)
+        want = [int(v) * linv % p for v in back][: n + m] + [0] * (N - (n + m))
+        np.testing.assert_array_equal(got, np.array(want, dtype=np.uint64))
+
+
+def _sizes_with_length(dm, N, seed):
+    """Unequal operand sizes (na, nb) whose plan picks transform length N."""
+    rng = random.Random(seed)
+    for _ in range(200):
+        frac = rng.uniform(0.70, 0.98)           # of the longest length N admits
+        ratio = rng.uniform(0.2, 0.8)
+        need = int(N * frac)
+        ga = max(1, int(need * ratio))
+        gb = max(1, need - ga)
+        na = max(1, ga * 15 // 19)
+        nb = max(1, gb * 15 // 19)
+        if dm.plan(na, nb).N == N:
+            return na, nb
+    raise AssertionError(f"no sizes found for N={N}")
+
+
+@pytest.mark.parametrize("e", list(range(4, 20)))
+def test_radix3_lengths_vs_oracle(dm, ctx, e):
+    """Every row layout of the transform lengths 3*2^e (rows of 3*2^logC
+    points, logC = 2..10) against the oracle, and against the power-of-two
+    path on the same operands."""
+    N = 3 << e
+    na, nb = _sizes_with_length(dm, N, e)
+    pl = dm.plan(na, nb)
+    assert pl.factor == 3 and pl.log2_n == e
+    _note(f"radix-3 N=3*2^{e} ({pl.log2_rows}x3*2^{pl.log2_cols}) {na}x{nb}")
+    rng = np.random.default_rng(7000 + e)
+    a = rng.integers(0, 10 ** 19, size=na, dtype=np.uint64)
+    b = rng.integers(0, 10 ** 19, size=nb, dtype=np.uint64)
+    got = _gpu_mul(dm, ctx, a, b)
+    np.testing.assert_array_equal(got, oracle.mul_ntt(a, b))
+    np.testing.assert_array_equal(_gpu_mul(dm, ctx, a, b, pow2=True), got)
+
+
+def _mod_pm(limbs):
+    """(X mod 10^19 - 1, X mod 10^19 + 1) of a limb array: since 10^19 is
+    1 resp. -1 modulo these, the (alternating) limb sums decide them."""
+    x = np.asarray(limbs, dtype=np.uint64)
+
+    def total(v):
+        return int(np.sum(v & np.uint64(0xFFFFFFFF))) + (int(np.sum(v >> np.uint64(32))) << 32)
+
+    M1, M2 = 10 ** 19 - 1, 10 ** 19 + 1
+    return total(x) % M1, (total(x[0::2]) - total(x[1::2])) % M2
+
+
+@pytest.mark.parametrize("e", [20, 22, 23])
+def test_radix3_long_rows_properties(dm, ctx, e):
+    """The longest layouts of 3*2^e (2^10..2^12 rows of 3*2^10..3*2^11 points), too
+    long for the oracle in a test: the product's residues modulo 10^19 - 1
+    and 10^19 + 1 (casting out, exact at any size) and equality with the
+    power-of-two path."""
+    N = 3 << e
+    na, nb = _sizes_with_length(dm, N, 100 + e)
+    pl = dm.plan(na, nb)
+    assert pl.factor == 3 and pl.log2_n == e
+    _note(f"radix-3 N=3*2^{e} ({pl.log2_rows}x3*2^{pl.log2_cols}) {na}x{nb} properties")
+    rng = np.random.default_rng(8000 + e)
+    a = rng.integers(0, 10 ** 19, size=na, dtype=np.uint64)
+    b = rng.integers(0, 10 ** 19, size=nb, dtype=np.uint64)
+    got = _gpu_mul(dm, ctx, a, b)
+    assert int(got.max()) < 10 ** 19
+    (a1, a2), (b1, b2), (z1, z2) = _mod_pm(a), _mod_pm(b), _mod_pm(got)
+    assert z1 == a1 * b1 % (10 ** 19 - 1)
+    assert z2 == a2 * b2 % (10 ** 19 + 1)
+    if pl.N < (1 << 26):
+        np.testing.assert_array_equal(_gpu_mul(dm, ctx, a, b, pow2=True), got)
 
 
 @pytest.mark.parametrize("n", [1, 2, 50, 81, 777, 5264])
@@ -163,12 +252,14 @@ def test_c1_100k_digits_vs_schoolbook(dm, ctx):
     np.testing.assert_array_equal(got, oracle.schoolbook(a, b))
 
 
-def test_c2_10m_digits_vs_oracle(dm, ctx):
-    _note("C2 10^7 x 10^7 random")
+@pytest.mark.parametrize("pow2", [False, True])
+def test_c2_10m_digits_vs_oracle(dm, ctx, pow2):
+    _note(f"C2 10^7 x 10^7 random pow2={pow2}")
     a = synth.random_operand(10 ** 7, 2001)
     b = synth.random_operand(10 ** 7, 2002)
-    got = _gpu_mul(dm, ctx, a, b)
-    np.testing.assert_array_equal(got, oracle.mul_ntt(a, b))
+    assert dm.plan(len(a), len(b), pow2=pow2).N == (1 << 21 if pow2 else 3 << 19)
+    got = _gpu_mul(dm, ctx, a, b, pow2=pow2)
+    np.testing.assert_array_equal(got, _oracle_mul("c2", a, b))
 
 
 def test_c2_all_nines_closed_form(dm, ctx):
@@ -179,13 +270,16 @@ def test_c2_all_nines_closed_form(dm, ctx):
     np.testing.assert_array_equal(got, _nines_square_limbs(d, 2 * len(a)))
 
 
-@pytest.mark.parametrize("force_k", [0, 14])
-def test_c3_unbalanced_vs_oracle(dm, ctx, force_k):
-    _note(f"C3 4e7 x 2e7 force_k={force_k}")
+@pytest.mark.parametrize("force_k,pow2", [(0, False), (14, False), (14, True)])
+def test_c3_unbalanced_vs_oracle(dm, ctx, force_k, pow2):
+    """C3 at its default k (N = 2^22, square layout), and at k = 14 both as
+    3*2^21 (2048 rows of 3*1024) and as the 2n x n power-of-two layout
+    2^23 = 2048 x 4096."""
+    _note(f"C3 4e7 x 2e7 force_k={force_k} pow2={pow2}")
     a = synth.random_operand(4 * 10 ** 7, 3001)
     b = synth.random_operand(2 * 10 ** 7, 3002)
-    got = _gpu_mul(dm, ctx, a, b, force_k=force_k)
-    np.testing.assert_array_equal(got, oracle.mul_ntt(a, b, force_k=force_k))
+    got = _gpu_mul(dm, ctx, a, b, force_k=force_k, pow2=pow2)
+    np.testing.assert_array_equal(got, _oracle_mul(("c3", force_k), a, b, force_k=force_k))
 
 
 def test_errors_and_empty(dm, ctx):
