@@ -276,7 +276,7 @@ int ensure_status(dmul_ctx* ctx, size_t n) {
 }
 
 // Recovery sync words (a counter and one map word per workgroup) for at
-// least `words` words; zeroed at allocation and left zeroed by every launch.
+// least `words` words (one carry map per recovery block, rewritten by every launch).
 int ensure_rec_sync(dmul_ctx* ctx, size_t words) {
   if (ctx->rec_sync_cap >= words) return DMUL_OK;
   hipError_t e = hipStreamSynchronize(ctx->stream);
@@ -589,8 +589,8 @@ int dmul_sync(dmul_ctx* c) {
   e = hipMemcpy(st.data(), c->d_status, n * sizeof(int), hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemset(c->d_status, 0, n * sizeof(int));
   if (e != hipSuccess) return from_hip(e);
-  // status bits: 1 = a limb >= 10^19, 2 = a device-side wait gave up
-  auto code = [](int w) { return (w & 2) ? DMUL_EDEVICE : ((w & 1) ? DMUL_EDIGIT : DMUL_OK); };
+  // status bit 1: a limb >= 10^19
+  auto code = [](int w) { return (w & 1) ? DMUL_EDIGIT : DMUL_OK; };
   if (st[0] && rc == DMUL_OK) rc = code(st[0]);
   if (c->batch_status) {
     for (size_t i = 0; i < c->batch_count; ++i)

@@ -39,7 +39,7 @@ class BatchEngine {
 
   uint64_t* ws_ = nullptr;          // per-product workspaces, back to back
   size_t ws_words_ = 0;
-  uint32_t* sync_ = nullptr;        // per-product recovery sync words (kept zero)
+  uint32_t* sync_ = nullptr;        // per-product recovery carry maps
   size_t sync_words_ = 0;
   ProdDesc* d_desc_ = nullptr;      // descriptors on the device
   ProdDesc* h_desc_ = nullptr;      // pinned staging copy

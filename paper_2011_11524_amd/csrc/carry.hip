@@ -26,6 +26,7 @@ namespace dmi {
 typedef unsigned __int128 u128;
 
 constexpr int kRecThreads = 256;
+constexpr int kScanThreads = 1024;
 
 __device__ __forceinline__ ProdDesc load_desc(const Work& w) {
   return w.many ? w.many[blockIdx.z] : w.one;
@@ -215,61 +216,60 @@ __device__ __forceinline__ uint64_t div_p10(uint64_t x, int e, const DivTable* _
   return __umul64hi(x >> e, dt->mag[e]) >> dt->sh[e];
 }
 
-constexpr uint32_t kMapValid = 1u << 8;
-
-__device__ __forceinline__ void map_store(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t map_load(uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Pass 1: CRT digits, s_i = q0_i + q1_(i-1) + q2_(i-2), and the carry map of
-// every workgroup's positions.  Thread 0 takes the four positions before the
-// workgroup (their q1, q2 feed its first s values), threads 1..256 take four
-// positions each; the digits are computed branch-free so the four
-// independent chains of a thread interleave.  The workgroup that finishes
-// last (a counter taken after a device-scope fence) scans the maps of all
-// workgroups and writes each one's incoming carry: no workgroup ever waits
-// for another.
+// every block of kRecThreads * PT positions (Section 8.2: the recovery is a
+// sequential carry; the maps make it a scan).  A workgroup loops over
+// blocks; thread t takes PT consecutive positions, lanes 0 and 1 also the
+// two positions before the block (their q1, q2 feed its first s values).
+// The digits are computed branch-free so the PT independent chains of a
+// thread interleave.  Each block's map is a plain store: the scan that
+// consumes the maps is the next launch.
 template <int PT>
-__global__ void __launch_bounds__(kRecThreads + 1)
+__global__ void __launch_bounds__(kRecThreads)
 k_rec_crt(Work w, RecTable rt) {
   const ProdDesc d = load_desc(w);
-  if (blockIdx.x >= d.nblk) return;
   const RecConsts rc = rec_consts(rt, d);
   const uint64_t* __restrict__ res1 = d.ws;
   const uint64_t* __restrict__ res2 = d.ws + d.pl.N;
   uint64_t* __restrict__ s_out = d.ws + 2 * d.pl.N;
-  uint32_t* __restrict__ cins = (uint32_t*)(s_out + rc.NP);
-  uint32_t* maps = d.rec_sync + 1;
-  uint32_t* counter = d.rec_sync;
-  int* status = d.status;
+  uint32_t* __restrict__ maps = d.rec_sync;
   constexpr int BLK = kRecThreads * PT;
   __shared__ uint64_t tail_q1[kRecThreads + 1], tail_q2a[kRecThreads + 1], tail_q2b[kRecThreads + 1];
-  __shared__ uint32_t s_last;
-  // positions base .. base+PT-1 (thread 0: the PT positions before the workgroup)
-  const int64_t base = (int64_t)blockIdx.x * BLK + ((int64_t)threadIdx.x - 1) * PT;
-  uint64_t a1[PT], a2[PT];
+  for (uint32_t blk = blockIdx.x; blk < d.nblk; blk += gridDim.x) {
+    const int64_t bbase = (int64_t)blk * BLK;
+    const int64_t base = bbase + (int64_t)threadIdx.x * PT;
+    uint64_t a1[PT], a2[PT];
 #pragma unroll
-  for (int u = 0; u < PT; ++u) {
-    const int64_t i = base + u;
-    const bool in = i >= 0 && (uint64_t)i < rc.NP;
-    a1[u] = in ? res1[i] : 0;
-    a2[u] = in ? res2[i] : 0;
-  }
-  uint64_t q0[PT], q1[PT], q2[PT];
+    for (int u = 0; u < PT; ++u) {
+      const int64_t i = base + u;
+      const bool in = (uint64_t)i < rc.NP;
+      a1[u] = in ? res1[i] : 0;
+      a2[u] = in ? res2[i] : 0;
+    }
+    uint64_t q0[PT], q1[PT], q2[PT];
 #pragma unroll
-  for (int u = 0; u < PT; ++u) crt_digits(a1[u], a2[u], rc, q0[u], q1[u], q2[u]);
-  tail_q1[threadIdx.x] = q1[PT - 1];
-  tail_q2a[threadIdx.x] = q2[PT - 1];
-  tail_q2b[threadIdx.x] = q2[PT - 2];
-  __syncthreads();
-  uint32_t f = kIdentityMap;
-  if (threadIdx.x > 0) {
-    const uint64_t pq1 = tail_q1[threadIdx.x - 1];
-    const uint64_t pq2_1 = tail_q2a[threadIdx.x - 1];
-    const uint64_t pq2_2 = tail_q2b[threadIdx.x - 1];
+    for (int u = 0; u < PT; ++u) crt_digits(a1[u], a2[u], rc, q0[u], q1[u], q2[u]);
+    if (threadIdx.x < 2) {
+      // position bbase-1 (lane 0) or bbase-2 (lane 1); zero before the start
+      const int64_t i = bbase - 1 - (int64_t)threadIdx.x;
+      const uint64_t x1 = i >= 0 ? res1[i] : 0, x2 = i >= 0 ? res2[i] : 0;
+      uint64_t p0, p1, p2;
+      crt_digits(x1, x2, rc, p0, p1, p2);
+      if (threadIdx.x == 0) {
+        tail_q1[0] = p1;
+        tail_q2a[0] = p2;
+      } else {
+        tail_q2b[0] = p2;
+      }
+    }
+    tail_q1[threadIdx.x + 1] = q1[PT - 1];
+    tail_q2a[threadIdx.x + 1] = q2[PT - 1];
+    tail_q2b[threadIdx.x + 1] = q2[PT - 2];
+    __syncthreads();
+    const uint64_t pq1 = tail_q1[threadIdx.x];
+    const uint64_t pq2_1 = tail_q2a[threadIdx.x];
+    const uint64_t pq2_2 = tail_q2b[threadIdx.x];
+    uint32_t f = kIdentityMap;
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
       const uint64_t prev_q1 = u >= 1 ? q1[u - 1] : pq1;
@@ -280,44 +280,35 @@ k_rec_crt(Work w, RecTable rt) {
         f = compose(carry_map(sv, rc.B), f);
       }
     }
+    uint32_t total;
+    block_exclusive_scan(f, &total);
+    if (threadIdx.x == 0) maps[blk] = total;
+    __syncthreads();   // the tail arrays and scan words are reused by the next block
   }
-  uint32_t total;
-  block_exclusive_scan(f, &total);
-  if (threadIdx.x == 0) {
-    map_store(&maps[blockIdx.x], kMapValid | total);
-    const uint32_t done = atomicAdd(counter, 1u);
-    s_last = done == rc.nblk - 1 ? 1u : 0u;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  // The last workgroup: exclusive scan over all workgroup maps.  A map word
-  // is used only once its valid bit is visible here (no fence needed; the
-  // wait is bounded), and the words are cleared again afterwards, so the
-  // launch leaves the buffer as it found it (and can be replayed).
-  const uint32_t nb = rc.nblk;
-  const uint32_t nth = blockDim.x;
-  const uint32_t per = (nb + nth - 1) / nth;
-  const uint32_t lo = threadIdx.x * per;
+}
+
+// Scan of the block maps: the incoming carry of every block (the carry into
+// position 0 is 0).  One workgroup per product; thread t composes a
+// contiguous run of maps, then the runs are scanned across the workgroup.
+__global__ void __launch_bounds__(kScanThreads)
+k_rec_scan(Work w, RecTable rt) {
+  const ProdDesc d = load_desc(w);
+  const RecConsts rc = rec_consts(rt, d);
+  const uint32_t* __restrict__ maps = d.rec_sync;
+  uint32_t* __restrict__ cins = (uint32_t*)(d.ws + 2 * d.pl.N + rc.NP);
+  const uint32_t nb = d.nblk;
+  const uint32_t per = (nb + kScanThreads - 1) / kScanThreads;
+  const uint32_t lo = threadIdx.x * per < nb ? threadIdx.x * per : nb;
   const uint32_t hi = lo + per < nb ? lo + per : nb;
   uint32_t g = kIdentityMap;
-  for (uint32_t b = lo; b < hi; ++b) {
-    uint32_t mw = map_load(&maps[b]);
-    for (uint32_t polls = 0; !(mw & kMapValid); ++polls) {
-      if (polls > (1u << 20)) { atomicOr(status, 2); break; }
-      __builtin_amdgcn_s_sleep(1);
-      mw = map_load(&maps[b]);
-    }
-    g = compose(mw & 63u, g);
-  }
+  for (uint32_t b = lo; b < hi; ++b) g = compose(maps[b], g);
   uint32_t all;
   const uint32_t before = block_exclusive_scan(g, &all);
   uint32_t c = apply_map(before, 0);
   for (uint32_t b = lo; b < hi; ++b) {
     cins[b] = c;
-    c = apply_map(map_load(&maps[b]) & 63u, c);
-    map_store(&maps[b], 0u);
+    c = apply_map(maps[b], c);
   }
-  if (threadIdx.x == 0) atomicExch(counter, 0u);   // every workgroup has counted: reset
 }
 
 // Pass 2: z_i = (s_i + carry_i) mod B from the workgroup's incoming carry and
@@ -329,7 +320,6 @@ __global__ void __launch_bounds__(kRecThreads)
 k_rec_apply(Work w, RecTable rt, const DivTable* __restrict__ dt_g) {
   constexpr int BLK = kRecThreads * PT;
   const ProdDesc d = load_desc(w);
-  if (blockIdx.x >= d.nblk) return;
   const RecConsts rc = rec_consts(rt, d);
   const uint64_t* __restrict__ s_in = d.ws + 2 * d.pl.N;
   const uint32_t* __restrict__ cins = (const uint32_t*)(s_in + rc.NP);
@@ -339,66 +329,69 @@ k_rec_apply(Work w, RecTable rt, const DivTable* __restrict__ dt_g) {
   for (unsigned i = threadIdx.x; i < sizeof(DivTable) / 4; i += blockDim.x)
     reinterpret_cast<uint32_t*>(&sdt)[i] = reinterpret_cast<const uint32_t*>(dt_g)[i];
   const DivTable* dt = &sdt;
-  const uint64_t bbase = (uint64_t)blockIdx.x * BLK;
-  const uint64_t base = bbase + (uint64_t)threadIdx.x * PT;
   const uint64_t B = rc.B;
-  uint64_t s[PT];
-  uint32_t f = kIdentityMap;
+  const uint64_t k = (uint64_t)rc.k;
+  for (uint32_t blk = blockIdx.x; blk < d.nblk; blk += gridDim.x) {
+    const uint64_t bbase = (uint64_t)blk * BLK;
+    const uint64_t base = bbase + (uint64_t)threadIdx.x * PT;
+    uint64_t s[PT];
+    uint32_t f = kIdentityMap;
 #pragma unroll
-  for (int u = 0; u < PT; ++u) {
-    const uint64_t i = base + u;
-    s[u] = i < rc.NP ? s_in[i] : 0;
-    if (i < rc.NP) f = compose(carry_map(s[u], B), f);
-  }
-  uint32_t total;
-  const uint32_t before = block_exclusive_scan(f, &total);
-  uint32_t c = apply_map(before, cins[blockIdx.x]);
+    for (int u = 0; u < PT; ++u) {
+      const uint64_t i = base + u;
+      s[u] = i < rc.NP ? s_in[i] : 0;
+      if (i < rc.NP) f = compose(carry_map(s[u], B), f);
+    }
+    uint32_t total;
+    const uint32_t before = block_exclusive_scan(f, &total);
+    uint32_t c = apply_map(before, cins[blk]);
 #pragma unroll
-  for (int u = 0; u < PT; ++u) {
-    uint64_t t = s[u] + c;
-    uint32_t o = 0;
-    if (t >= B) { t -= B; o = 1; }
-    if (t >= B) { t -= B; o = 2; }
-    z[threadIdx.x * PT + u] = t;
-    c = o;
-  }
-  if (threadIdx.x == kRecThreads - 1) {
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const uint64_t i = bbase + BLK + u;
-      uint64_t t = (i < rc.NP ? s_in[i] : 0) + c;
+    for (int u = 0; u < PT; ++u) {
+      uint64_t t = s[u] + c;
       uint32_t o = 0;
       if (t >= B) { t -= B; o = 1; }
       if (t >= B) { t -= B; o = 2; }
-      z[BLK + u] = t;
+      z[threadIdx.x * PT + u] = t;
       c = o;
     }
-  }
-  __syncthreads();
-
-  // limbs j with first digit 19j in [k*bbase, k*(bbase + BLK))
-  const uint64_t k = (uint64_t)rc.k;
-  const uint64_t d_lo = k * bbase, d_hi = k * (bbase + BLK);
-  const uint64_t j_lo = (d_lo + 18) / 19;
-  uint64_t j_hi = (d_hi + 18) / 19;
-  if (j_hi > rc.nout) j_hi = rc.nout;
-  for (uint64_t j = j_lo + threadIdx.x; j < j_hi; j += kRecThreads) {
-    const uint32_t d0 = (uint32_t)(19 * j - d_lo);     // digit offset inside the workgroup, < 2^17
-    const uint32_t i0 = (uint32_t)(((uint64_t)d0 * rc.kinv) >> 22);
-    const int o = (int)(d0 - i0 * (uint32_t)rc.k);
-    const int have0 = rc.k - o;
-    uint64_t limb = div_p10(z[i0], o, dt);
-    const int need = 19 - have0;
-    if (need <= rc.k) {
-      const uint64_t z1 = z[i0 + 1];
-      limb += (z1 - div_p10(z1, need, dt) * dt->pow10[need]) * dt->pow10[have0];
-    } else {
-      const int need2 = need - rc.k;
-      const uint64_t z2 = z[i0 + 2];
-      limb += z[i0 + 1] * dt->pow10[have0];
-      limb += (z2 - div_p10(z2, need2, dt) * dt->pow10[need2]) * dt->pow10[have0 + rc.k];
+    if (threadIdx.x == kRecThreads - 1) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const uint64_t i = bbase + BLK + u;
+        uint64_t t = (i < rc.NP ? s_in[i] : 0) + c;
+        uint32_t o = 0;
+        if (t >= B) { t -= B; o = 1; }
+        if (t >= B) { t -= B; o = 2; }
+        z[BLK + u] = t;
+        c = o;
+      }
     }
-    out[j] = limb;
+    __syncthreads();
+
+    // limbs j with first digit 19j in [k*bbase, k*(bbase + BLK))
+    const uint64_t d_lo = k * bbase, d_hi = k * (bbase + BLK);
+    const uint64_t j_lo = (d_lo + 18) / 19;
+    uint64_t j_hi = (d_hi + 18) / 19;
+    if (j_hi > rc.nout) j_hi = rc.nout;
+    for (uint64_t j = j_lo + threadIdx.x; j < j_hi; j += kRecThreads) {
+      const uint32_t d0 = (uint32_t)(19 * j - d_lo);     // digit offset inside the block, < 2^17
+      const uint32_t i0 = (uint32_t)(((uint64_t)d0 * rc.kinv) >> 22);
+      const int o = (int)(d0 - i0 * (uint32_t)rc.k);
+      const int have0 = rc.k - o;
+      uint64_t limb = div_p10(z[i0], o, dt);
+      const int need = 19 - have0;
+      if (need <= rc.k) {
+        const uint64_t z1 = z[i0 + 1];
+        limb += (z1 - div_p10(z1, need, dt) * dt->pow10[need]) * dt->pow10[have0];
+      } else {
+        const int need2 = need - rc.k;
+        const uint64_t z2 = z[i0 + 2];
+        limb += z[i0 + 1] * dt->pow10[have0];
+        limb += (z2 - div_p10(z2, need2, dt) * dt->pow10[need2]) * dt->pow10[have0 + rc.k];
+      }
+      out[j] = limb;
+    }
+    __syncthreads();   // z is reused by the next block
   }
 }
 
@@ -416,6 +409,13 @@ size_t recover_blocks(const PlanDev& pl) {
 
 size_t recover_scratch_words(const PlanDev& pl) {
   return (size_t)(pl.n + pl.m) + recover_blocks(pl) + 1;   // s, then carries (u32)
+}
+
+// Workgroups of the grid-stride recovery passes: enough to fill the device
+// (a few per CU), never more than the blocks of the longest product.
+static unsigned recover_grid(uint32_t max_nblk) {
+  const uint32_t cap = 256 * 6;
+  return max_nblk < cap ? (max_nblk ? max_nblk : 1) : cap;
 }
 
 hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, const DivTable* dt,
@@ -439,9 +439,11 @@ hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, cons
     rt.bsh[i] = dt_host->sh[k];
     rt.inv_B[i] = 1.0 / (double)B;
   }
-  hipLaunchKernelGGL(k_rec_crt<kRecPT>, dim3(sh.max_nblk, 1, w.count), dim3(kRecThreads + 1), 0, st, w, rt);
+  const unsigned g = recover_grid(sh.max_nblk);
+  hipLaunchKernelGGL(k_rec_crt<kRecPT>, dim3(g, 1, w.count), dim3(kRecThreads), 0, st, w, rt);
+  hipLaunchKernelGGL(k_rec_scan, dim3(1, 1, w.count), dim3(kScanThreads), 0, st, w, rt);
   if (marks) marks->mark(kRecCrt, st);
-  hipLaunchKernelGGL(k_rec_apply<kRecPT>, dim3(sh.max_nblk, 1, w.count), dim3(kRecThreads), 0, st, w, rt, dt);
+  hipLaunchKernelGGL(k_rec_apply<kRecPT>, dim3(g, 1, w.count), dim3(kRecThreads), 0, st, w, rt, dt);
   if (marks) marks->mark(kRecApply, st);
   return hipGetLastError();
 }

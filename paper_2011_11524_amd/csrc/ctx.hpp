@@ -97,7 +97,7 @@ struct dmul_ctx {
   size_t batch_count = 0;
   dmi::BatchEngine* batch = nullptr;
   dmi::Profiler* prof = nullptr;
-  uint32_t* rec_sync = nullptr;         // recovery: [0] counter, [1..] map words (kept zero)
+  uint32_t* rec_sync = nullptr;         // recovery: one carry map per block
   size_t rec_sync_cap = 0;
   dmi::TuneTable tune;                  // per transform length launch parameters
   std::mutex mu;

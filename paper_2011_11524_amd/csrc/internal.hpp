@@ -91,8 +91,8 @@ struct ProdDesc {
   const uint64_t* b;
   uint64_t* out;            // na + nb result limbs
   uint64_t* ws;             // 4N words: X1 X2 Y1 Y2 (recovery scratch reuses Y)
-  int* status;              // bit 1: a limb >= 10^19; bit 2: a device-side wait gave up
-  uint32_t* rec_sync;       // [0] counter, [1..nblk] map words; zero between launches
+  int* status;              // bit 1: a limb >= 10^19 (set by the split)
+  uint32_t* rec_sync;       // recovery: the carry map of each block (nblk words)
   uint32_t nblk;            // recovery workgroups
   int square;               // a == b: one operand transformed
 };
