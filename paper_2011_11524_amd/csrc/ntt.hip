@@ -118,8 +118,26 @@ struct Round {
   }
 };
 
-// Rounds R, R+1, ... of a full transform; a __syncthreads() separates rounds.
-template <int LOGL, int LOGE, bool DIT, int R>
+// Synchronisation between the rounds of in-LDS transforms.  When every
+// transform is owned by threads of one wavefront (NT <= 64, a power of two,
+// so no transform straddles two wavefronts), the wavefront's own LDS writes
+// need only be complete before it reads them back: a workgroup-scope fence
+// (which waits for them) and a wavefront barrier order that, and the
+// workgroup's wavefronts run their rounds without waiting for each other.
+// Otherwise the workgroup barrier.
+template <bool WAVE>
+__device__ __forceinline__ void round_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Rounds R, R+1, ... of a full transform; a round_sync follows every round.
+template <int LOGL, int LOGE, bool DIT, int R, bool WAVE>
 struct Rounds {
   using G = Geometry<LOGL, LOGE>;
   static constexpr int LO_B = DIT ? R * LOGE : (LOGL - (R + 1) * LOGE > 0 ? LOGL - (R + 1) * LOGE : 0);
@@ -127,12 +145,12 @@ struct Rounds {
   static __device__ __forceinline__ void run(uint64_t* lds, const uint64_t* __restrict__ tw,
                                              const Prime& P, int t, bool active) {
     if (active) Round<LOGL, LOGE, DIT, LO_B, HI_B - LO_B>::run(lds, tw, P, t);
-    __syncthreads();
-    Rounds<LOGL, LOGE, DIT, R + 1>::run(lds, tw, P, t, active);
+    round_sync<WAVE>();
+    Rounds<LOGL, LOGE, DIT, R + 1, WAVE>::run(lds, tw, P, t, active);
   }
 };
-template <int LOGL, int LOGE, bool DIT>
-struct Rounds<LOGL, LOGE, DIT, (LOGL + LOGE - 1) / LOGE> {
+template <int LOGL, int LOGE, bool DIT, bool WAVE>
+struct Rounds<LOGL, LOGE, DIT, (LOGL + LOGE - 1) / LOGE, WAVE> {
   static __device__ __forceinline__ void run(uint64_t*, const uint64_t* __restrict__, const Prime&,
                                              int, bool) {}
 };
@@ -140,31 +158,33 @@ struct Rounds<LOGL, LOGE, DIT, (LOGL + LOGE - 1) / LOGE> {
 // Bounds of round R of a DIF (top bits first) or DIT (bottom bits first) transform.
 template <int LOGL, int LOGE, bool DIT, int R>
 struct RoundBits {
-  static constexpr int LO_B = Rounds<LOGL, LOGE, DIT, R>::LO_B;
-  static constexpr int NB = Rounds<LOGL, LOGE, DIT, R>::HI_B - LO_B;
+  static constexpr int LO_B = Rounds<LOGL, LOGE, DIT, R, false>::LO_B;
+  static constexpr int NB = Rounds<LOGL, LOGE, DIT, R, false>::HI_B - LO_B;
   using type = Round<LOGL, LOGE, DIT, LO_B, NB>;
 };
 
-// Rounds [R, END) through LDS, a barrier after each.
-template <int LOGL, int LOGE, bool DIT, int R, int END>
+// Rounds [R, END) through LDS, a round_sync after each.
+template <int LOGL, int LOGE, bool DIT, int R, int END, bool WAVE>
 struct RoundRange {
   static __device__ __forceinline__ void run(uint64_t* lds, const uint64_t* __restrict__ tw,
                                              const Prime& P, int t) {
     if constexpr (R < END) {
       RoundBits<LOGL, LOGE, DIT, R>::type::run(lds, tw, P, t);
-      __syncthreads();
-      RoundRange<LOGL, LOGE, DIT, R + 1, END>::run(lds, tw, P, t);
+      round_sync<WAVE>();
+      RoundRange<LOGL, LOGE, DIT, R + 1, END, WAVE>::run(lds, tw, P, t);
     }
   }
 };
 
 // In-LDS transform of 2^LOGL points (DIF natural->bit-reversed, or DIT
 // bit-reversed->natural), run by the workgroup; `active` threads own a
-// transform, the others only take part in the barriers.
-template <int LOGL, int LOGE, bool DIT>
+// transform, the others only take part in the synchronisation.  With WAVE
+// the caller synchronises the workgroup before other wavefronts read the
+// result.
+template <int LOGL, int LOGE, bool DIT, bool WAVE>
 __device__ __forceinline__ void lds_transform(uint64_t* lds, const uint64_t* __restrict__ tw,
                                               const Prime& P, int t, bool active) {
-  Rounds<LOGL, LOGE, DIT, 0>::run(lds, tw, P, t, active);
+  Rounds<LOGL, LOGE, DIT, 0, WAVE>::run(lds, tw, P, t, active);
 }
 
 // ---------------------------------------------------------------------------
@@ -276,6 +296,7 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
   constexpr int NTH = T * G::NT;                 // threads
   constexpr int PER = (R * T + NTH - 1) / NTH;   // tile points per thread
   constexpr int TS = Tile<T, R3>::TS;
+  constexpr bool kWave = G::NT <= 64;            // each column within one wavefront
   extern __shared__ uint64_t lds[];
   uint64_t* troots = lds + T * G::STRIDE;        // [prime][R/2]
   const ProdDesc d = load_desc(w);
@@ -324,7 +345,8 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
       }
       __syncthreads();
     }
-    lds_transform<LOGR, LOGE, false>(lds + col * G::STRIDE, troots + pi * (R / 2), P, t, true);
+    lds_transform<LOGR, LOGE, false, kWave>(lds + col * G::STRIDE, troots + pi * (R / 2), P, t, true);
+    if constexpr (kWave) __syncthreads();
     if constexpr (!R3) {
       for (int q = threadIdx.x; q < R * T; q += NTH) {
         const int row = q / T, c = q % T;
@@ -384,6 +406,7 @@ k_rows(Work w, Consts cs, TwiddleSet tw) {
   using G = Geometry<LOGC, LOGE>;
   constexpr int C = G::L, E = G::E, NT = G::NT;
   constexpr int NR = G::ROUNDS;
+  constexpr bool kWave = NT <= 64;               // each row within one wavefront
   extern __shared__ uint64_t lds[];
   const ProdDesc d = load_desc(w);
   const int y = blockIdx.y;
@@ -424,8 +447,8 @@ k_rows(Work w, Consts cs, TwiddleSet tw) {
       using R0 = typename RoundBits<LOGC, LOGE, false, 0>::type;
       R0::compute(cur, roots, P, t);
       R0::store(row_lds, cur, t);
-      __syncthreads();
-      RoundRange<LOGC, LOGE, false, 1, NR>::run(row_lds, roots, P, t);
+      round_sync<kWave>();
+      RoundRange<LOGC, LOGE, false, 1, NR, kWave>::run(row_lds, roots, P, t);
       // points back to the coalesced layout
 #pragma unroll
       for (int j = 0; j < E; ++j) cur[j] = row_lds[lds_pos<LOGE>(t + j * NT)];
@@ -436,8 +459,8 @@ k_rows(Work w, Consts cs, TwiddleSet tw) {
     } else {
 #pragma unroll
       for (int j = 0; j < E; ++j) row_lds[lds_pos<LOGE>(t + j * NT)] = cur[j];
-      __syncthreads();
-      RoundRange<LOGC, LOGE, true, 0, NR - 1>::run(row_lds, roots, P, t);
+      round_sync<kWave>();
+      RoundRange<LOGC, LOGE, true, 0, NR - 1, kWave>::run(row_lds, roots, P, t);
       // last round (top bits) ends in the coalesced layout
       using RL = typename RoundBits<LOGC, LOGE, true, NR - 1>::type;
       RL::load(row_lds, cur, t);
@@ -447,7 +470,7 @@ k_rows(Work w, Consts cs, TwiddleSet tw) {
         for (int j = 0; j < E; ++j) X[row * C + RL::index(t, j)] = cur[j];
       }
     }
-    __syncthreads();   // the next group reuses the LDS rows
+    round_sync<kWave>();   // the next group reuses the LDS rows
   }
 }
 
@@ -463,6 +486,7 @@ __global__ void __launch_bounds__((T * Geometry<LOGR, LOGE>::NT))
 k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   using G = Geometry<LOGR, LOGE>;
   constexpr int TS = Tile<T, R3>::TS;
+  constexpr bool kWave = G::NT <= 64;            // each column within one wavefront
   extern __shared__ uint64_t lds[];
   uint64_t* troots = lds + T * G::STRIDE;
   const ProdDesc d = load_desc(w);
@@ -514,7 +538,8 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   }
   __syncthreads();
   const int col = threadIdx.x / G::NT, t = threadIdx.x % G::NT;
-  lds_transform<LOGR, LOGE, true>(lds + col * G::STRIDE, troots, P, t, true);
+  lds_transform<LOGR, LOGE, true, kWave>(lds + col * G::STRIDE, troots, P, t, true);
+  if constexpr (kWave) __syncthreads();
   for (int q = threadIdx.x; q < R * T; q += blockDim.x) {
     const int row = q / T, c = q % T;
     if (tile.valid(c)) X[(uint64_t)row * C + tile.column(c)] = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
@@ -525,16 +550,18 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
 // Launch configuration and dispatch over the compile-time lengths.
 // ---------------------------------------------------------------------------
 constexpr int loge_for(int logl) { return logl < 4 ? logl : 4; }
+// Points per thread (log2) in the column passes.
+constexpr int col_loge(int logl) { return loge_for(logl); }
 // LDS words a workgroup may use (160 KB per CU, less the static tables).
 constexpr int kLdsWords = (160 * 1024 - 1024) / 8;
-constexpr int col_stride(int logl) { return (1 << logl) + ((1 << logl) >> loge_for(logl)) + 1; }
+constexpr int col_stride(int logl) { return (1 << logl) + ((1 << logl) >> col_loge(logl)) + 1; }
 // Column tiles: as many columns as fit a target workgroup size (at most 64)
 // and the LDS next to `extra` words of tables.  Wide tiles matter: every
 // global access of a column pass is a run of T contiguous words of one row,
 // and runs below a 128-byte line waste HBM transactions.
 constexpr int cols_for(int logl, int threads, int extra) {
   int t = 1;
-  while (t < 64 && 2 * t * (1 << (logl - loge_for(logl))) <= threads &&
+  while (t < 64 && 2 * t * (1 << (logl - col_loge(logl))) <= threads &&
          2 * t * col_stride(logl) + extra <= kLdsWords)
     t *= 2;
   return t;
@@ -543,7 +570,7 @@ constexpr int cols_for(int logl, int threads, int extra) {
 // the thread target and the LDS.
 constexpr int triples_for(int logl, int threads, int extra) {
   int t = 1;
-  while (t < 16 && 2 * t * 3 * (1 << (logl - loge_for(logl))) <= threads &&
+  while (t < 16 && 2 * t * 3 * (1 << (logl - col_loge(logl))) <= threads &&
          2 * t * 3 * col_stride(logl) + extra <= kLdsWords)
     t *= 2;
   return t;
@@ -569,7 +596,7 @@ static hipError_t prepare(K kernel, size_t lds_bytes) {
 template <int LOGR, bool R3>
 static hipError_t fwd_cols_launch(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                                   const DivTable* dt, hipStream_t st) {
-  constexpr int LOGE = loge_for(LOGR);
+  constexpr int LOGE = col_loge(LOGR);
   constexpr int T = R3 ? 3 * fwd_triples_per_tile(LOGR) : fwd_cols_per_tile(LOGR);
   constexpr int TS = R3 ? T / 3 : T;
   using G = Geometry<LOGR, LOGE>;
@@ -615,7 +642,7 @@ static hipError_t rows_l(const Work& w, const Shape& sh, const Consts& cs, const
 template <int LOGR, bool R3>
 static hipError_t inv_cols_launch(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                                   hipStream_t st) {
-  constexpr int LOGE = loge_for(LOGR);
+  constexpr int LOGE = col_loge(LOGR);
   constexpr int T = R3 ? 3 * triples_per_tile(LOGR) : cols_per_tile(LOGR);
   constexpr int TS = R3 ? T / 3 : T;
   using G = Geometry<LOGR, LOGE>;
