@@ -169,10 +169,10 @@ def run_batched(dm, ctx, torch, steps: int, warmup: int, count: int):
     # completion latency of every product, one profiled repetition per mode
     ctx.profile(True)
     one_by_one()
-    ev = [t for ph, t in ctx.profile_events() if ph == "rec_apply"]
+    ev = [t for ph, t in ctx.profile_events() if ph in ("rec_apply", "whole")]
     lat_pp = ev[:count]
     batched()
-    ev = [t for ph, t in ctx.profile_events() if ph == "rec_apply"]
+    ev = [t for ph, t in ctx.profile_events() if ph in ("rec_apply", "whole")]
     ctx.profile(False)
     classes = sorted(set(lens))
     done = {c: ev[i] for i, c in enumerate(classes)} if len(ev) == len(classes) else {}

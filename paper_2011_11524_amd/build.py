@@ -8,8 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdmul.so")
-SOURCES = ["api.hip", "batch.hip", "ntt.hip", "carry.hip"]
-HEADERS = ["field.hpp", "internal.hpp", "ctx.hpp", "batch.hpp"]
+SOURCES = ["api.hip", "batch.hip", "ntt.hip", "carry.hip", "small.hip"]
+HEADERS = ["field.hpp", "internal.hpp", "ctx.hpp", "batch.hpp", "ntt_dev.hpp", "rec_dev.hpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -220,6 +220,8 @@ int get_twiddles(dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw) {
       }
     }
     PassTables pt;
+    for (int i = 0; i < 2; ++i)
+      pt.scale[i] = to_mont(mulmod(to_mont(1, kP[i]), inv_mod(N % kP[i], kP[i]), kP[i]), kP[i]);
     hipError_t e = hipMalloc(&pt.dev, h.size() * sizeof(uint64_t));
     if (e != hipSuccess) return from_hip(e);
     e = hipMemcpy(pt.dev, h.data(), h.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
@@ -235,6 +237,7 @@ int get_twiddles(dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw) {
     tw->lo_fwd[i] = base + HI;
     tw->hi_inv[i] = base + HI + LO;
     tw->lo_inv[i] = base + 2 * HI + LO;
+    tw->scale[i] = it->second.scale[i];
   }
   return DMUL_OK;
 }
@@ -354,6 +357,8 @@ int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t*
   Shape sh{pl.logR, pl.logC, pl.rad3, d.square ? 0 : 1, row_iters_for(ctx, pl), d.nblk};
   Marks* marks = ctx->prof;
   if (ctx->prof) ctx->prof->begin(ctx->stream);
+  if (!residues && small_fits(pl))
+    return from_hip(launch_small(w, sh, ctx->cs, tw, ctx->d_div, &ctx->h_div, ctx->stream, marks));
   hipError_t e = launch_forward(w, sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
   if (e == hipSuccess) e = launch_inverse(w, sh, ctx->cs, tw, ctx->stream, marks);
   if (e != hipSuccess) return from_hip(e);
@@ -697,7 +702,7 @@ int dmul_ctx_profile_events(dmul_ctx* c, int32_t* phases, double* end_ms, int n)
 
 const char* dmul_phase_name(int phase) {
   static const char* names[kNumPhases] = {"fwd_cols", "fwd_rows", "inv_rows", "inv_cols",
-                                          "rec_crt", "rec_apply"};
+                                          "rec_crt", "rec_apply", "whole"};
   return (phase >= 0 && phase < kNumPhases) ? names[phase] : "unknown";
 }
 

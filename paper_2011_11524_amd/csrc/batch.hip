@@ -191,6 +191,10 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       Work w{};
       w.many = descs + c.first + off;
       w.count = (uint32_t)std::min<size_t>(65535, c.n - off);
+      if (small_fits(c.p0)) {
+        e = launch_small(w, c.sh, ctx->cs, tw, ctx->d_div, &ctx->h_div, ctx->stream, marks);
+        continue;
+      }
       e = launch_forward(w, c.sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
       if (e == hipSuccess) e = launch_inverse(w, c.sh, ctx->cs, tw, ctx->stream, marks);
       if (e == hipSuccess) e = launch_recover(w, c.sh, ctx->cs, ctx->d_div, &ctx->h_div, ctx->stream, marks);

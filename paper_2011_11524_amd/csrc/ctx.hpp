@@ -17,6 +17,7 @@ struct TuneTable {
   int row_iters[2][kMaxLogN + 1] = {};
 };
 struct PassTables {
+  uint64_t scale[2] = {};     // R^2 N^-1 mod p per prime
   uint64_t* dev = nullptr;   // per prime: hi_fwd[N >> lb] lo_fwd[2^lb] hi_inv[N >> lb] lo_inv[2^lb]
 };
 

@@ -13,6 +13,7 @@ constexpr int kMaxLogLen = 13;     // longest sub-transform held in one workgrou
 constexpr int kMaxLogC3 = 11;      // rows of 3 * 2^logC points: logC <= 11
 constexpr int kMaxLogR3 = 12;      // with C = 3M a column tile holds three columns of 2^logR points
 constexpr int kMinLogN3 = 4;       // lengths 3 * 2^e are used for e >= 4
+constexpr uint64_t kSmallMaxN = 4096;   // whole product in one workgroup up to this length
 constexpr int kMinK = 13;          // p1*p2 < 10^(3k): three base-10^k parts per coefficient
 constexpr uint64_t kLimbBase = 10000000000000000000ULL;  // 10^19
 
@@ -62,6 +63,7 @@ struct TwiddleSet {
   const uint64_t* len_inv[2];   // [prime] -> same for inverse roots
   const uint64_t* r3_fwd[2];    // [prime] -> base of the radix-3 row tables (forward)
   const uint64_t* r3_inv[2];    // [prime] -> same, inverse
+  uint64_t scale[2];            // [prime] R^2 N^-1 mod p (Montgomery form of R N^-1)
   const uint64_t* hi_fwd[2];
   const uint64_t* lo_fwd[2];
   const uint64_t* hi_inv[2];
@@ -78,7 +80,7 @@ constexpr size_t kR3TableWords = 2 * (((size_t)1 << (kMaxLogC3 + 1)) - 1);
 
 // Optional per-kernel timing: when set, a launch wrapper records an event on
 // the stream after each kernel it launches (phase ids below).
-enum Phase { kFwdCols = 0, kFwdRows, kInvRows, kInvCols, kRecCrt, kRecApply, kNumPhases };
+enum Phase { kFwdCols = 0, kFwdRows, kInvRows, kInvCols, kRecCrt, kRecApply, kWhole, kNumPhases };
 struct Marks {
   virtual void mark(int phase, hipStream_t st) = 0;
   virtual ~Marks() = default;
@@ -121,6 +123,10 @@ hipError_t launch_inverse(const Work& w, const Shape& sh, const Consts& cs, cons
                           hipStream_t stream, Marks* marks);
 hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, const DivTable* dt,
                           const DivTable* dt_host, hipStream_t stream, Marks* marks);
+// Whole products in one workgroup (small.hip), for N <= kSmallMaxN.
+bool small_fits(const PlanDev& pl);
+hipError_t launch_small(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                        const DivTable* dt, const DivTable* dt_host, hipStream_t stream, Marks* marks);
 size_t recover_blocks(const PlanDev& pl);
 size_t recover_scratch_words(const PlanDev& pl);
 hipError_t launch_zero(uint64_t* out, size_t n, hipStream_t stream);

@@ -1,0 +1,219 @@
+// Whole products in one workgroup, for short transforms (N <= kSmallMaxN).
+//
+// A product whose transform fits the LDS of one workgroup runs every step
+// of the method in one kernel: digit-group split (Section 3.2), for each
+// prime the forward transforms of both operands, the pointwise REDC
+// product, the inverse transform and the scale R^2 N^-1 (Sections 5, 6),
+// then the CRT digits, the carry scan and the regrouping into base-10^19
+// limbs (Section 8.2).  The transform is one in-LDS pass (no inter-pass
+// factor): DIF natural -> bit-reversed, DIT back (Section 5.4).  For
+// N = 3M the length-3 DFT across the thirds and the factors w_N^(+-s*q)
+// come first (forward) or last (inverse), around three M-point transforms
+// (Section 7.8).  A batch launches one workgroup per product of the class:
+// the many short products of a batch cost one launch instead of seven.
+#include "rec_dev.hpp"
+
+namespace dmi {
+
+constexpr int kSmallThreads = 256;
+
+template <int LOGM>
+struct SmallGeom {
+  static constexpr int LOGE = LOGM < 4 ? LOGM : 4;
+  using G = Geometry<LOGM, LOGE>;
+};
+
+// LDS words of the whole-product kernel: X and Y (F sub-rows each, padded
+// layout) and the digit array Q (N + 2 words).
+constexpr size_t small_lds_words(int logm, int f) {
+  return 2 * (size_t)f * (((size_t)1 << logm) + (((size_t)1 << logm) >> (logm < 4 ? logm : 4)) + 1) +
+         ((size_t)f << logm) + 2;
+}
+
+template <int LOGM, bool R3>
+__global__ void __launch_bounds__(kSmallThreads)
+k_small(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g, RecTable rt) {
+  constexpr int LOGE = SmallGeom<LOGM>::LOGE;
+  using G = typename SmallGeom<LOGM>::G;
+  constexpr int M = G::L, NT = G::NT, S = G::STRIDE;
+  constexpr int F = R3 ? 3 : 1;
+  constexpr int N = F * M;
+  constexpr bool kWave = NT <= 64;
+  static_assert(NT <= kSmallThreads, "one transform per workgroup at most");
+  constexpr int PER_PASS = kSmallThreads / NT;       // sub-transforms run side by side
+  extern __shared__ uint64_t lds[];
+  uint64_t* X = lds;                 // operand a, then the product, then q1
+  uint64_t* Y = lds + F * S;         // operand b, then q2
+  uint64_t* Q = lds + 2 * F * S;     // residues mod p1, then q0, then the digits z
+  __shared__ DivTable sdt;
+  for (unsigned i = threadIdx.x; i < sizeof(DivTable) / 4; i += blockDim.x)
+    reinterpret_cast<uint32_t*>(&sdt)[i] = reinterpret_cast<const uint32_t*>(dt_g)[i];
+  const DivTable* dt = &sdt;
+  const ProdDesc d = load_desc(w);
+  const RecConsts rc = rec_consts(rt, d);
+  const bool square = d.square != 0;
+  const int nsub = square ? F : 2 * F;
+  // point n of an operand (natural order) lives at sub-row n / M, slot n mod M
+  auto at = [&](uint64_t* A, int n) -> uint64_t& { return A[(n / M) * S + lds_pos<LOGE>(n % M)]; };
+
+#pragma unroll 1
+  for (int pi = 0; pi < 2; ++pi) {
+    const Prime P = cs.P[pi];
+    for (int n = threadIdx.x; n < N; n += kSmallThreads) {
+      at(X, n) = split_group(d.a, d.pl.na, d.pl.n, (uint64_t)n, d.pl.k, dt, d.status);
+      if (!square) at(Y, n) = split_group(d.b, d.pl.nb, d.pl.m, (uint64_t)n, d.pl.k, dt, d.status);
+    }
+    __syncthreads();
+    if constexpr (R3) {
+      const uint64_t* w3 = tw.r3_fwd[pi] + r3_table_offset(LOGM);
+      for (int j = threadIdx.x; j < (square ? M : 2 * M); j += kSmallThreads) {
+        uint64_t* A = j < M ? X : Y;
+        const int q = j % M, o = lds_pos<LOGE>(q);
+        uint64_t x0 = A[o], x1 = A[S + o], x2 = A[2 * S + o];
+        dft3(x0, x1, x2, cs.kappa[pi][0], P);
+        A[o] = x0;
+        A[S + o] = mont_mul(x1, w3[q], P);
+        A[2 * S + o] = mont_mul(x2, w3[2 * q], P);
+      }
+      __syncthreads();
+    }
+    const uint64_t* rf = tw.len_fwd[pi] + root_table_offset(LOGM);
+    for (int b0 = 0; b0 < nsub; b0 += PER_PASS) {
+      const int idx = b0 + (int)threadIdx.x / NT;
+      const bool active = (int)threadIdx.x / NT < PER_PASS && idx < nsub;
+      uint64_t* A = !active ? X : (idx < F ? X + idx * S : Y + (idx - F) * S);
+      lds_transform<LOGM, LOGE, false, kWave>(A, rf, P, (int)threadIdx.x % NT, active);
+    }
+    __syncthreads();
+    for (int n = threadIdx.x; n < N; n += kSmallThreads) {
+      uint64_t& x = at(X, n);
+      x = mont_mul(x, square ? x : at(Y, n), P);
+    }
+    __syncthreads();
+    const uint64_t* ri = tw.len_inv[pi] + root_table_offset(LOGM);
+    for (int b0 = 0; b0 < F; b0 += PER_PASS) {
+      const int idx = b0 + (int)threadIdx.x / NT;
+      const bool active = (int)threadIdx.x / NT < PER_PASS && idx < F;
+      lds_transform<LOGM, LOGE, true, kWave>(active ? X + idx * S : X, ri, P, (int)threadIdx.x % NT, active);
+    }
+    __syncthreads();
+    // (inverse length-3 step), the scale R^2 N^-1; residues of p1 go to Q
+    const uint64_t scale = tw.scale[pi];
+    for (int q = threadIdx.x; q < M; q += kSmallThreads) {
+      const int o = lds_pos<LOGE>(q);
+      uint64_t x[F];
+#pragma unroll
+      for (int s = 0; s < F; ++s) x[s] = X[s * S + o];
+      if constexpr (R3) {
+        const uint64_t* w3 = tw.r3_inv[pi] + r3_table_offset(LOGM);
+        x[1] = mont_mul(x[1], w3[q], P);
+        x[2] = mont_mul(x[2], w3[2 * q], P);
+        dft3(x[0], x[1], x[2], cs.kappa[pi][1], P);
+      }
+#pragma unroll
+      for (int s = 0; s < F; ++s) {
+        const uint64_t v = mont_mul(x[s], scale, P);
+        if (pi == 0) Q[s * M + q] = v;
+        else X[s * S + o] = v;
+      }
+    }
+    __syncthreads();
+  }
+
+  // CRT digits in place: q0 -> Q, q1 -> X, q2 -> Y
+  const int NP = (int)rc.NP;
+  for (int i = threadIdx.x; i < NP; i += kSmallThreads) {
+    uint64_t q0, q1, q2;
+    crt_digits(Q[i], at(X, i), rc, q0, q1, q2);
+    Q[i] = q0;
+    at(X, i) = q1;
+    at(Y, i) = q2;
+  }
+  if (threadIdx.x < 2) Q[N + threadIdx.x] = 0;
+  __syncthreads();
+  // carries: thread t owns positions [t*per, t*per + per)
+  const int per = (NP + kSmallThreads - 1) / kSmallThreads;
+  const int lo = (int)threadIdx.x * per < NP ? (int)threadIdx.x * per : NP;
+  const int hi = lo + per < NP ? lo + per : NP;
+  auto s_at = [&](int i) -> uint64_t {
+    return Q[i] + (i >= 1 ? at(X, i - 1) : 0) + (i >= 2 ? at(Y, i - 2) : 0);
+  };
+  uint32_t f = kIdentityMap;
+  for (int i = lo; i < hi; ++i) f = compose(carry_map(s_at(i), rc.B), f);
+  uint32_t total;
+  const uint32_t before = block_exclusive_scan(f, &total);
+  uint32_t c = apply_map(before, 0);
+  for (int i = lo; i < hi; ++i) {
+    uint64_t t = s_at(i) + c;
+    uint32_t o = 0;
+    if (t >= rc.B) { t -= rc.B; o = 1; }
+    if (t >= rc.B) { t -= rc.B; o = 2; }
+    Q[i] = t;
+    c = o;
+  }
+  for (int i = NP + (int)threadIdx.x; i < N; i += kSmallThreads) Q[i] = 0;
+  __syncthreads();
+  // regroup: limb j holds decimal digits [19j, 19j + 19)
+  const int k = rc.k;
+  for (uint64_t j = threadIdx.x; j < rc.nout; j += kSmallThreads) {
+    const uint32_t d0 = (uint32_t)(19 * j);             // < 2^17
+    const uint32_t i0 = (uint32_t)(((uint64_t)d0 * rc.kinv) >> 22);
+    const int o = (int)(d0 - i0 * (uint32_t)k);
+    const int have0 = k - o;
+    uint64_t limb = div_p10(Q[i0], o, dt);
+    const int need = 19 - have0;
+    if (need <= k) {
+      const uint64_t z1 = Q[i0 + 1];
+      limb += (z1 - div_p10(z1, need, dt) * dt->pow10[need]) * dt->pow10[have0];
+    } else {
+      const int need2 = need - k;
+      const uint64_t z2 = Q[i0 + 2];
+      limb += Q[i0 + 1] * dt->pow10[have0];
+      limb += (z2 - div_p10(z2, need2, dt) * dt->pow10[need2]) * dt->pow10[have0 + k];
+    }
+    d.out[j] = limb;
+  }
+}
+
+template <int LOGM, bool R3>
+static hipError_t small_launch(const Work& w, const Consts& cs, const TwiddleSet& tw, const DivTable* dt,
+                               const RecTable& rt, hipStream_t st) {
+  const size_t lds = small_lds_words(LOGM, R3 ? 3 : 1) * sizeof(uint64_t);
+  auto kern = k_small<LOGM, R3>;
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(1, 1, w.count), dim3(kSmallThreads), lds, st, w, cs, tw, dt, rt);
+  return hipGetLastError();
+}
+
+bool small_fits(const PlanDev& pl) { return pl.N <= (uint64_t)kSmallMaxN; }
+
+hipError_t launch_small(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                        const DivTable* dt, const DivTable* dt_host, hipStream_t st, Marks* marks) {
+  const RecTable rt = make_rec_table(cs, dt_host);
+  // N = 2^logN, or 3 * 2^logN with rad3: the sub-transforms have 2^logN points
+  const int logm = sh.logR + sh.logC;
+  hipError_t e = hipErrorInvalidValue;
+  if (sh.rad3) {
+    switch (logm) {
+#define X(l) case l: e = small_launch<l, true>(w, cs, tw, dt, rt, st); break;
+      X(4) X(5) X(6) X(7) X(8) X(9) X(10)
+#undef X
+      default: break;
+    }
+  } else {
+    switch (logm) {
+#define X(l) case l: e = small_launch<l, false>(w, cs, tw, dt, rt, st); break;
+      X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
+#undef X
+      default: break;
+    }
+  }
+  if (e == hipSuccess && marks) marks->mark(kWhole, st);
+  return e;
+}
+
+}  // namespace dmi

@@ -171,6 +171,60 @@ def test_radix3_lengths_vs_oracle(dm, ctx, e):
     np.testing.assert_array_equal(_gpu_mul(dm, ctx, a, b, pow2=True), got)
 
 
+def _small_classes():
+    """Transform lengths of the one-workgroup kernel: 2^2..2^12 and 3*2^4..3*2^10."""
+    return sorted([1 << e for e in range(2, 13)] + [3 << e for e in range(4, 11)])
+
+
+def _sizes_at_most(dm, N, seed):
+    """Operand sizes (na, nb) whose plan picks length N, drawn near the top
+    of the class (so that the longest products of the class are covered)."""
+    rng = random.Random(seed)
+    for _ in range(400):
+        na = rng.randint(1, max(1, N * 13 // 19))
+        nb = rng.randint(1, max(1, N * 13 // 19))
+        try:
+            if dm.plan(na, nb).N == N:
+                return na, nb
+        except dm.DmulError:
+            pass
+    for na in range(1, N):
+        if dm.plan(na, na).N == N:
+            return na, na
+    raise AssertionError(f"no sizes for N={N}")
+
+
+def test_whole_product_kernel_every_class(dm, ctx):
+    """Every transform length of the one-workgroup kernel (N <= 4096), each
+    as a single product and as one batch of all of them, products and
+    squares, against the oracle."""
+    import torch
+    rng = np.random.default_rng(9100)
+    cases = []
+    for N in _small_classes():
+        na, nb = _sizes_at_most(dm, N, N)
+        a = rng.integers(0, 10 ** 19, size=na, dtype=np.uint64)
+        b = rng.integers(0, 10 ** 19, size=nb, dtype=np.uint64)
+        cases.append((N, a, b))
+    pairs, want = [], []
+    for N, a, b in cases:
+        _note(f"whole-product N={N} {len(a)}x{len(b)}")
+        w = oracle.mul_ntt(a, b)
+        np.testing.assert_array_equal(_gpu_mul(dm, ctx, a, b), w)
+        da, db = dm.to_device(a), dm.to_device(b)
+        pairs.append((da, db))
+        want.append(w)
+        sq = _gpu_mul(dm, ctx, a, a)
+        np.testing.assert_array_equal(sq, oracle.mul_ntt(a, a))
+        pairs.append((da, da))
+        want.append(sq)
+    _note("whole-product batch")
+    outs, st = ctx.batch(pairs)
+    assert st == [0] * len(pairs)
+    for o, w in zip(outs, want):
+        np.testing.assert_array_equal(dm.to_host(o), w)
+
+
 def _mod_pm(limbs):
     """(X mod 10^19 - 1, X mod 10^19 + 1) of a limb array: since 10^19 is
     1 resp. -1 modulo these, the (alternating) limb sums decide them."""
