@@ -75,7 +75,8 @@ def phase_work(N: int, logR: int, logC: int, factor: int, arrays_fwd: int, NP: i
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("field.hpp", "ntt.hip", "carry.hip", "internal.hpp"):
+    for f in ("field.hpp", "internal.hpp", "ntt_dev.hpp", "rec_dev.hpp", "ntt.hip", "carry.hip",
+              "small.hip"):
         with open(os.path.join(ROOT, "paper_2011_11524_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

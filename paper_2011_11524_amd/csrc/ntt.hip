@@ -78,7 +78,7 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
   const uint64_t nl = op ? d.pl.nb : d.pl.na;
   const uint64_t ng = op ? d.pl.m : d.pl.n;
   const uint64_t N = d.pl.N;
-  const Tile<T, R3> tile(blockIdx.x, d.pl.logC, d.pl.rad3);
+  const Tile<T, R3> tile(xcd_tile(blockIdx.x, gridDim.x), d.pl.logC, d.pl.rad3);
   const uint64_t C = tile.C;
   const int lb = pass_split_bits(d.pl.logC, d.pl.rad3);
   __shared__ DivTable sdt;
@@ -123,11 +123,11 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
       for (int q = threadIdx.x; q < R * T; q += NTH) {
         const int row = q / T, c = q % T;
         if (!tile.valid(c)) continue;
-        const uint64_t j = tile.column(c);
-        const uint64_t e = (uint64_t)bitrev(row, LOGR) * j;
+        const uint32_t j = (uint32_t)tile.column(c);
+        const uint32_t e = __umul24(bitrev(row, LOGR), j);     // < N <= 2^26
         uint64_t x = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
         x = mont_mul(x, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], e, lb, P), P);
-        dst[(uint64_t)row * C + j] = x;
+        dst[(uint32_t)row * (uint32_t)C + j] = x;
       }
     } else {
       const uint64_t* w3 = tw.r3_fwd[pi] + r3_table_offset(d.pl.logC);
@@ -135,19 +135,20 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
       for (int q = threadIdx.x; q < R * TS; q += NTH) {
         const int row = q / TS, c = q % TS;
         if (!tile.valid(c)) continue;
-        const uint64_t qc = tile.first + c;
-        const uint64_t rv = bitrev(row, LOGR);
+        const uint32_t qc = (uint32_t)tile.first + c;
+        const uint32_t rv = bitrev(row, LOGR);
+        const uint32_t e0 = __umul24(rv, qc), eM = __umul24(rv, (uint32_t)M);   // rv*(s*M + qc) < N
         const int o = lds_pos<LOGE>(row);
         uint64_t x0 = lds[c * G::STRIDE + o];
         uint64_t x1 = lds[(TS + c) * G::STRIDE + o];
         uint64_t x2 = lds[(2 * TS + c) * G::STRIDE + o];
-        x0 = mont_mul(x0, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], rv * qc, lb, P), P);
-        x1 = mont_mul(x1, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], rv * (M + qc), lb, P), P);
-        x2 = mont_mul(x2, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], rv * (2 * M + qc), lb, P), P);
+        x0 = mont_mul(x0, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], e0, lb, P), P);
+        x1 = mont_mul(x1, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], e0 + eM, lb, P), P);
+        x2 = mont_mul(x2, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], e0 + 2 * eM, lb, P), P);
         dft3(x0, x1, x2, cs.kappa[pi][0], P);
         x1 = mont_mul(x1, w3[qc], P);
         x2 = mont_mul(x2, w3[2 * qc], P);
-        uint64_t* rowp = dst + (uint64_t)row * C + qc;
+        uint64_t* rowp = dst + ((uint32_t)row * (uint32_t)C + qc);
         rowp[0] = x0;
         rowp[M] = x1;
         rowp[2 * M] = x2;
@@ -265,7 +266,7 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   const int pi = blockIdx.y;
   const Prime P = cs.P[pi];
   uint64_t* X = d.ws + (size_t)pi * d.pl.N;
-  const Tile<T, R3> tile(blockIdx.x, d.pl.logC, d.pl.rad3);
+  const Tile<T, R3> tile(xcd_tile(blockIdx.x, gridDim.x), d.pl.logC, d.pl.rad3);
   const uint64_t C = tile.C;
   const int lb = pass_split_bits(d.pl.logC, d.pl.rad3);
   constexpr int R = G::L;
@@ -277,9 +278,9 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
       const int row = q / T, c = q % T;
       uint64_t v = 0;
       if (tile.valid(c)) {
-        const uint64_t j = tile.column(c);
-        const uint64_t e = (uint64_t)bitrev(row, LOGR) * j;
-        v = X[(uint64_t)row * C + j];
+        const uint32_t j = (uint32_t)tile.column(c);
+        const uint32_t e = __umul24(bitrev(row, LOGR), j);     // < N <= 2^26
+        v = X[(uint32_t)row * (uint32_t)C + j];
         v = mont_mul(v, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], e, lb, P), P);
       }
       lds[c * G::STRIDE + lds_pos<LOGE>(row)] = v;
@@ -292,16 +293,17 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
       const int o = lds_pos<LOGE>(row);
       uint64_t x0 = 0, x1 = 0, x2 = 0;
       if (tile.valid(c)) {
-        const uint64_t qc = tile.first + c;
-        const uint64_t* rowp = X + (uint64_t)row * C + qc;
+        const uint32_t qc = (uint32_t)tile.first + c;
+        const uint64_t* rowp = X + ((uint32_t)row * (uint32_t)C + qc);
         x0 = rowp[0];
         x1 = mont_mul(rowp[M], w3[qc], P);
         x2 = mont_mul(rowp[2 * M], w3[2 * qc], P);
         dft3(x0, x1, x2, cs.kappa[pi][1], P);
-        const uint64_t rv = bitrev(row, LOGR);
-        x0 = mont_mul(x0, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], rv * qc, lb, P), P);
-        x1 = mont_mul(x1, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], rv * (M + qc), lb, P), P);
-        x2 = mont_mul(x2, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], rv * (2 * M + qc), lb, P), P);
+        const uint32_t rv = bitrev(row, LOGR);
+        const uint32_t e0 = __umul24(rv, qc), eM = __umul24(rv, (uint32_t)M);   // rv*(s*M + qc) < N
+        x0 = mont_mul(x0, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], e0, lb, P), P);
+        x1 = mont_mul(x1, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], e0 + eM, lb, P), P);
+        x2 = mont_mul(x2, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], e0 + 2 * eM, lb, P), P);
       }
       lds[c * G::STRIDE + o] = x0;
       lds[(TS + c) * G::STRIDE + o] = x1;
@@ -314,7 +316,8 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   if constexpr (kWave) __syncthreads();
   for (int q = threadIdx.x; q < R * T; q += blockDim.x) {
     const int row = q / T, c = q % T;
-    if (tile.valid(c)) X[(uint64_t)row * C + tile.column(c)] = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
+    if (tile.valid(c))
+      X[(uint32_t)row * (uint32_t)C + (uint32_t)tile.column(c)] = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
   }
 }
 

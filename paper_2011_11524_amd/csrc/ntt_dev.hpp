@@ -200,10 +200,11 @@ __device__ __forceinline__ uint32_t bitrev(uint32_t i, int bits) {
 }
 
 // Inter-pass factor xi_N^(+-e) (times the inverse scale), e = e_hi*2^lb + e_lo.
+// Exponents are below N <= 2^26 and fit 32 bits.
 __device__ __forceinline__ uint64_t pass_factor(const uint64_t* __restrict__ hi,
-                                                const uint64_t* __restrict__ lo, uint64_t e,
+                                                const uint64_t* __restrict__ lo, uint32_t e,
                                                 int lb, const Prime& P) {
-  const uint64_t L1 = ((uint64_t)1 << lb) - 1;
+  const uint32_t L1 = (1u << lb) - 1;
   return mont_mul(hi[e >> lb], lo[e & L1], P);
 }
 
@@ -225,6 +226,16 @@ __device__ __forceinline__ void dft3(uint64_t& a, uint64_t& b, uint64_t& c, uint
   a = add_mod(a, bc, P);
   b = add_mod(m, v, P);
   c = sub_mod(m, v, P);
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b to XCD
+// b mod 8), and each XCD has its own L2.  This bijection of [0, n) gives
+// every XCD a contiguous range of tiles, so tiles that share cache lines
+// (adjacent column tiles, whose rows meet inside 128-byte lines) meet in
+// the same L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
+  const uint32_t x = b % 8, i = b / 8, per = n / 8, rem = n % 8;
+  return x * per + (x < rem ? x : rem) + i;
 }
 
 // The product a kernel works on: the launch's single descriptor, or entry
