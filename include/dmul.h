@@ -181,6 +181,51 @@ int dmul_ctx_profile_read(dmul_ctx* ctx, double* total_ms, uint64_t* launches, i
 int dmul_ctx_profile_events(dmul_ctx* ctx, int32_t* phases, double* end_ms, int n);
 const char* dmul_phase_name(int phase);
 
+/* Cached transforms (transform reuse, the self-convolution idea of
+ * Section 6 carried across products): the forward transforms of one operand
+ * modulo both primes, kept on the device so that products with it skip
+ * them.  A spectrum is made for the plan (dmul_plan) of its operand with a
+ * partner of nb limbs under `flags` (DMUL_FLAG_FORCE_K, DMUL_FLAG_POW2), and
+ * serves every product whose plan has the same digit-group size k and
+ * transform length N, whatever the partner; other products fail with
+ * DMUL_EINVAL.
+ *
+ * dmul_spectrum_create: a: device pointer to na limbs (only read by the
+ *   work enqueued here: it may be freed once that work is done).  Enqueues
+ *   the transforms on ctx's stream; a limb >= 10^19 is reported by the next
+ *   dmul_sync (DMUL_EDIGIT).  The spectrum owns dmul_spectrum_bytes(na, nb,
+ *   flags) = 16 N bytes of device memory, outside the context's budget,
+ *   until dmul_spectrum_destroy.  Returns DMUL_OK and *spec, or DMUL_EINVAL
+ *   (NULL, empty operand, bad flags), DMUL_ERANGE, DMUL_ENOMEM, DMUL_EDEVICE.
+ * dmul_spectrum_destroy: frees it; the caller makes sure no queued work
+ *   still reads it (dmul_sync on every context that used it).
+ * Spectra belong to the device of the context that made them; use them on
+ * another stream only after dmul_sync on the creating context. */
+typedef struct dmul_spectrum dmul_spectrum;
+int dmul_spectrum_create(dmul_ctx* ctx, const uint64_t* a, size_t na, size_t nb, unsigned flags,
+                         dmul_spectrum** spec);
+int dmul_spectrum_destroy(dmul_spectrum* spec);
+size_t dmul_spectrum_bytes(size_t na, size_t nb, unsigned flags);
+
+/* dmul_ex_spectrum: like dmul_ex with X given by its spectrum sa (X has
+ * sa's na limbs), and Y given either by limbs (b, nb: device pointer, sb
+ * NULL) or by its spectrum sb (then b must be NULL and nb equal sb's limb
+ * count).  sa == sb squares.  out: na + nb limbs, not overlapping b.  flags
+ * as for the spectra.  Asynchronous on ctx's stream (dmul_sync completes
+ * it).  Returns DMUL_OK or a negative DMUL_E* code (DMUL_EINVAL also when
+ * the product's plan differs from a spectrum's). */
+int dmul_ex_spectrum(dmul_ctx* ctx, const dmul_spectrum* sa, const uint64_t* b, size_t nb,
+                     const dmul_spectrum* sb, uint64_t* out, unsigned flags);
+
+/* dmul_batch_ex: dmul_batch where operands may come as spectra.  sa and sb
+ * are NULL or host arrays of count spectrum pointers; where sa[i] is not
+ * NULL, a[i] is ignored and na[i] must equal its limb count (likewise b).
+ * A product whose plan does not match its spectra gets status DMUL_EINVAL. */
+int dmul_batch_ex(dmul_ctx* ctx, size_t count, const uint64_t* const* a, const size_t* na,
+                  const dmul_spectrum* const* sa, const uint64_t* const* b, const size_t* nb,
+                  const dmul_spectrum* const* sb, uint64_t* const* out, int32_t* status,
+                  unsigned flags);
+
 /* Size-class tuning: for products of transform length transform_len
  * (2^e or 3 * 2^e), every workgroup of the row pass loops over `row_iters`
  * groups of rows (0 = the default).  Contexts start from the table written

@@ -35,7 +35,9 @@ DMUL_FLAG_POW2 = 0x200
 EXPORTS = ("dmul", "dmul_ctx_create", "dmul_ctx_destroy", "dmul_ctx_set_stream", "dmul_ex",
            "dmul_sync", "dmul_batch", "dmul_plan", "dmul_workspace_bytes", "dmul_strerror",
            "dmul_host", "dmul_primes", "dmul_debug_residues", "dmul_version", "dmul_ctx_profile",
-           "dmul_ctx_profile_read", "dmul_phase_name", "dmul_ctx_profile_events", "dmul_ctx_tune")
+           "dmul_ctx_profile_read", "dmul_phase_name", "dmul_ctx_profile_events", "dmul_ctx_tune",
+           "dmul_spectrum_create", "dmul_spectrum_destroy", "dmul_spectrum_bytes", "dmul_ex_spectrum",
+           "dmul_batch_ex")
 
 
 class DmulError(RuntimeError):
@@ -107,6 +109,14 @@ def lib():
     L.dmul_ctx_profile_events.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     L.dmul_ctx_tune.argtypes = [vp, ctypes.c_uint64, ctypes.c_int]
+    L.dmul_spectrum_create.argtypes = [vp, vp, sz, sz, ctypes.c_uint, ctypes.POINTER(vp)]
+    L.dmul_spectrum_destroy.argtypes = [vp]
+    L.dmul_spectrum_bytes.argtypes = [sz, sz, ctypes.c_uint]
+    L.dmul_spectrum_bytes.restype = sz
+    L.dmul_ex_spectrum.argtypes = [vp, vp, vp, sz, vp, vp, ctypes.c_uint]
+    L.dmul_batch_ex.argtypes = [vp, sz, ctypes.POINTER(vp), ctypes.POINTER(sz), ctypes.POINTER(vp),
+                                ctypes.POINTER(vp), ctypes.POINTER(sz), ctypes.POINTER(vp),
+                                ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int32), ctypes.c_uint]
     L.dmul_phase_name.argtypes = [ctypes.c_int]
     L.dmul_phase_name.restype = ctypes.c_char_p
     _lib = L
@@ -142,6 +152,33 @@ def plan(na: int, nb: int, force_k: int = 0, pow2: bool = False) -> Plan:
 
 def workspace_bytes(na: int, nb: int) -> int:
     return int(lib().dmul_workspace_bytes(int(na), int(nb)))
+
+
+def spectrum_bytes(na: int, nb: int, force_k: int = 0, pow2: bool = False) -> int:
+    return int(lib().dmul_spectrum_bytes(int(na), int(nb), flags_for(force_k, pow2)))
+
+
+class Spectrum:
+    """Cached forward transforms of one operand (dmul_spectrum): made by
+    Context.spectrum, used in place of the operand's limbs."""
+
+    def __init__(self, handle, na: int, nb_plan: int, flags: int, owner):
+        self._h = handle
+        self.na = int(na)
+        self.nb_plan = int(nb_plan)
+        self.flags = int(flags)
+        self._lib = owner._lib
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.dmul_spectrum_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _check_limbs(t, name: str):
@@ -214,36 +251,88 @@ class Context:
         self.sync()
         return out
 
+    # -- cached transforms ---------------------------------------------------
+    def spectrum(self, a, nb: int, force_k: int = 0, pow2: bool = False) -> "Spectrum":
+        """Forward transforms of a for products with partners of nb limbs
+        (valid for every partner with the same plan k and N)."""
+        _check_limbs(a, "a")
+        h = ctypes.c_void_p()
+        flags = flags_for(force_k, pow2)
+        rc = self._lib.dmul_spectrum_create(self._h, ctypes.c_void_p(a.data_ptr()), a.numel(), int(nb),
+                                            flags, ctypes.byref(h))
+        if rc:
+            raise DmulError(rc, "dmul_spectrum_create")
+        return Spectrum(h, a.numel(), nb, flags, self)
+
+    def mul_spectrum_async(self, sa: "Spectrum", b, out, sb: "Spectrum" = None, force_k: int = 0,
+                           pow2: bool = False) -> None:
+        """out = X * Y with X from its spectrum sa, Y from limbs b or (b None)
+        from its spectrum sb."""
+        _check_limbs(out, "out")
+        if sb is not None:
+            nb, bp = sb.na, None
+        else:
+            _check_limbs(b, "b")
+            nb, bp = b.numel(), b.data_ptr()
+        if out.numel() != sa.na + nb:
+            raise ValueError("out must hold na + nb limbs")
+        rc = self._lib.dmul_ex_spectrum(self._h, sa._h, ctypes.c_void_p(bp) if bp else None, nb,
+                                        sb._h if sb is not None else None,
+                                        ctypes.c_void_p(out.data_ptr()), flags_for(force_k, pow2))
+        if rc:
+            raise DmulError(rc, "dmul_ex_spectrum")
+
+    def mul_spectrum(self, sa: "Spectrum", b=None, sb: "Spectrum" = None, force_k: int = 0,
+                     pow2: bool = False):
+        nb = sb.na if sb is not None else b.numel()
+        out = torch.empty(sa.na + nb, dtype=torch.uint64, device=f"cuda:{self.device}")
+        self.mul_spectrum_async(sa, b, out, sb, force_k, pow2)
+        self.sync()
+        return out
+
     # -- batches -------------------------------------------------------------
     def batch_async(self, pairs: Sequence, outs: Sequence, force_k: int = 0, graph: bool = False,
                     pow2: bool = False):
         """Enqueue len(pairs) products (a_i, b_i) -> outs[i]; returns the host
-        status array that sync() fills in.  graph=True captures the batch in
-        a HIP graph, replayed when the same batch is submitted again."""
+        status array that sync() fills in.  An operand may be a Spectrum of
+        this context's device instead of a tensor.  graph=True captures the
+        batch in a HIP graph, replayed when the same batch is submitted
+        again."""
         n = len(pairs)
         A = (ctypes.c_void_p * n)()
         B = (ctypes.c_void_p * n)()
+        SA = (ctypes.c_void_p * n)()
+        SB = (ctypes.c_void_p * n)()
         O = (ctypes.c_void_p * n)()
         NA = (ctypes.c_size_t * n)()
         NB = (ctypes.c_size_t * n)()
         st = (ctypes.c_int32 * n)()
+        spectra = False
         for i, ((a, b), o) in enumerate(zip(pairs, outs)):
-            A[i] = a.data_ptr() if a.numel() else 0
-            B[i] = b.data_ptr() if b.numel() else 0
+            for x, P, S, L in ((a, A, SA, NA), (b, B, SB, NB)):
+                if isinstance(x, Spectrum):
+                    S[i] = x._h.value
+                    L[i] = x.na
+                    spectra = True
+                else:
+                    P[i] = x.data_ptr() if x.numel() else 0
+                    L[i] = x.numel()
             O[i] = o.data_ptr() if o.numel() else 0
-            NA[i] = a.numel()
-            NB[i] = b.numel()
         flags = flags_for(force_k, pow2) | (DMUL_FLAG_GRAPH if graph else 0)
-        rc = self._lib.dmul_batch(self._h, n, A, NA, B, NB, O, st, flags)
+        if spectra:
+            rc = self._lib.dmul_batch_ex(self._h, n, A, NA, SA, B, NB, SB, O, st, flags)
+        else:
+            rc = self._lib.dmul_batch(self._h, n, A, NA, B, NB, O, st, flags)
         if rc:
             raise DmulError(rc, "dmul_batch")
-        self._keep = (A, B, O, NA, NB)
+        self._keep = (A, B, SA, SB, O, NA, NB)
         return st
 
     def batch(self, pairs: Sequence, force_k: int = 0, graph: bool = False, outs=None,
               pow2: bool = False):
         if outs is None:
-            outs = [torch.empty(a.numel() + b.numel(), dtype=torch.uint64, device=a.device)
+            size = lambda x: x.na if isinstance(x, Spectrum) else x.numel()
+            outs = [torch.empty(size(a) + size(b), dtype=torch.uint64, device=f"cuda:{self.device}")
                     for a, b in pairs]
         st = self.batch_async(pairs, outs, force_k, graph, pow2)
         self.sync()

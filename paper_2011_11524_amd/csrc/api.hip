@@ -328,11 +328,27 @@ int check_args(const uint64_t* a, size_t na, const uint64_t* b, size_t nb, const
 // Enqueues one whole product; `status` is the device word its bad-limb
 // check reports to.  With `residues` set, stops after the convolution and
 // copies both residue vectors there instead of recovering the answer.
+// The plan of a product whose operands may come as cached spectra: the plan
+// of (na, nb) must have the k and transform length every given spectrum was
+// made for (DMUL_EINVAL otherwise).
+int spectrum_plan(const dmul_spectrum* sa, size_t na, const dmul_spectrum* sb, size_t nb,
+                  unsigned flags, PlanDev* pl) {
+  if ((sa && sa->na != na) || (sb && sb->na != nb)) return DMUL_EINVAL;
+  const int rc = make_plan(na, nb, flags, pl);
+  if (rc) return rc;
+  for (const dmul_spectrum* s : {sa, sb}) {
+    if (s && (s->pl.k != pl->k || s->pl.N != pl->N || s->pl.logR != pl->logR || s->pl.rad3 != pl->rad3))
+      return DMUL_EINVAL;
+  }
+  return DMUL_OK;
+}
+
 int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
-                    uint64_t* out, unsigned flags, int* status, uint64_t* residues) {
+                    uint64_t* out, unsigned flags, int* status, uint64_t* residues,
+                    const dmul_spectrum* sa, const dmul_spectrum* sb) {
   if (na == 0 || nb == 0) return from_hip(launch_zero(out, na + nb, ctx->stream));
   PlanDev pl;
-  int rc = make_plan(na, nb, flags, &pl);
+  int rc = spectrum_plan(sa, na, sb, nb, flags, &pl);
   if (rc) return rc;
   TwiddleSet tw;
   rc = get_twiddles(ctx, pl, &tw);
@@ -351,13 +367,15 @@ int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t*
   d.status = status;
   d.rec_sync = ctx->rec_sync;
   d.nblk = (uint32_t)recover_blocks(pl);
-  d.square = (a == b && na == nb) ? 1 : 0;
+  d.square = (sa || sb) ? (sa == sb ? 1 : 0) : ((a == b && na == nb) ? 1 : 0);
+  d.xs = sa ? sa->dev : nullptr;
+  d.ys = sb ? sb->dev : nullptr;
   w.many = nullptr;
   w.count = 1;
   Shape sh{pl.logR, pl.logC, pl.rad3, d.square ? 0 : 1, row_iters_for(ctx, pl), d.nblk};
   Marks* marks = ctx->prof;
   if (ctx->prof) ctx->prof->begin(ctx->stream);
-  if (!residues && small_fits(pl))
+  if (!residues && !sa && !sb && small_fits(pl))
     return from_hip(launch_small(w, sh, ctx->cs, tw, ctx->d_div, &ctx->h_div, ctx->stream, marks));
   hipError_t e = launch_forward(w, sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
   if (e == hipSuccess) e = launch_inverse(w, sh, ctx->cs, tw, ctx->stream, marks);
@@ -706,14 +724,20 @@ const char* dmul_phase_name(int phase) {
   return (phase >= 0 && phase < kNumPhases) ? names[phase] : "unknown";
 }
 
-int dmul_batch(dmul_ctx* c, size_t count, const uint64_t* const* a, const size_t* na,
-               const uint64_t* const* b, const size_t* nb, uint64_t* const* out,
-               int32_t* status, unsigned flags) {
+int dmul_batch_ex(dmul_ctx* c, size_t count, const uint64_t* const* a, const size_t* na,
+                  const dmul_spectrum* const* sa, const uint64_t* const* b, const size_t* nb,
+                  const dmul_spectrum* const* sb, uint64_t* const* out, int32_t* status,
+                  unsigned flags) {
   if (!c || (count && (!a || !na || !b || !nb || !out || !status))) return DMUL_EINVAL;
   if (flags & ~(DMUL_FLAG_K_MASK | DMUL_FLAG_POW2 | DMUL_FLAG_GRAPH)) return DMUL_EINVAL;
   for (size_t i = 0; i < count; ++i) {
-    const int rc = check_args(a[i], na[i], b[i], nb[i], out[i]);
+    const dmul_spectrum* si = sa ? sa[i] : nullptr;
+    const dmul_spectrum* ti = sb ? sb[i] : nullptr;
+    if ((si && si->na != na[i]) || (ti && ti->na != nb[i])) return DMUL_EINVAL;
+    // an operand given by its spectrum needs no limbs
+    const int rc = check_args(a[i], si ? 0 : na[i], b[i], ti ? 0 : nb[i], out[i]);
     if (rc) return rc;
+    if ((si || ti) && !out[i]) return DMUL_EINVAL;
   }
   std::lock_guard<std::mutex> lk(c->mu);
   int rc = ensure_status(c, 1 + count);
@@ -723,9 +747,89 @@ int dmul_batch(dmul_ctx* c, size_t count, const uint64_t* const* a, const size_t
     c->batch = new (std::nothrow) BatchEngine();
     if (!c->batch) return DMUL_ENOMEM;
   }
-  rc = c->batch->run(c, count, a, na, b, nb, out, status, flags, c->d_status + 1);
+  rc = c->batch->run(c, count, a, na, sa, b, nb, sb, out, status, flags, c->d_status + 1);
   c->batch_status = status;
   c->batch_count = count;
+  if (rc == DMUL_EDEVICE && c->pending == DMUL_OK) c->pending = rc;
+  return rc;
+}
+
+int dmul_batch(dmul_ctx* c, size_t count, const uint64_t* const* a, const size_t* na,
+               const uint64_t* const* b, const size_t* nb, uint64_t* const* out,
+               int32_t* status, unsigned flags) {
+  return dmul_batch_ex(c, count, a, na, nullptr, b, nb, nullptr, out, status, flags);
+}
+
+size_t dmul_spectrum_bytes(size_t na, size_t nb, unsigned flags) {
+  PlanDev pl;
+  if (na == 0 || nb == 0 || make_plan(na, nb, flags & (DMUL_FLAG_K_MASK | DMUL_FLAG_POW2), &pl)) return 0;
+  return 2 * (size_t)pl.N * sizeof(uint64_t);
+}
+
+int dmul_spectrum_create(dmul_ctx* c, const uint64_t* a, size_t na, size_t nb, unsigned flags,
+                         dmul_spectrum** out) {
+  if (!c || !out) return DMUL_EINVAL;
+  *out = nullptr;
+  if (!a || na == 0 || nb == 0) return DMUL_EINVAL;
+  PlanDev pl;
+  int rc = make_plan(na, nb, flags, &pl);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  TwiddleSet tw;
+  rc = get_twiddles(c, pl, &tw);
+  if (rc) return rc;
+  dmul_spectrum* s = new (std::nothrow) dmul_spectrum;
+  if (!s) return DMUL_ENOMEM;
+  s->device = c->device;
+  s->na = na;
+  s->flags = flags;
+  s->pl = pl;
+  hipError_t e = hipMalloc(&s->dev, 2 * (size_t)pl.N * sizeof(uint64_t));
+  if (e != hipSuccess) {
+    delete s;
+    return from_hip(e);
+  }
+  // the forward passes of a squared product transform one operand into the
+  // first 2N words of the workspace: here, the spectrum's own buffer
+  Work w{};
+  ProdDesc& d = w.one;
+  d.pl = pl;
+  d.a = a;
+  d.b = a;
+  d.ws = s->dev;
+  d.status = c->d_status;
+  d.square = 1;
+  w.count = 1;
+  const Shape sh{pl.logR, pl.logC, pl.rad3, 0, row_iters_for(c, pl), 0};
+  e = launch_forward(w, sh, c->cs, tw, c->d_div, c->stream, nullptr);
+  if (e != hipSuccess) {
+    (void)hipFree(s->dev);
+    delete s;
+    if (c->pending == DMUL_OK) c->pending = DMUL_EDEVICE;
+    return from_hip(e);
+  }
+  *out = s;
+  return DMUL_OK;
+}
+
+int dmul_spectrum_destroy(dmul_spectrum* s) {
+  if (!s) return DMUL_EINVAL;
+  if (s->dev) (void)hipFree(s->dev);
+  delete s;
+  return DMUL_OK;
+}
+
+int dmul_ex_spectrum(dmul_ctx* c, const dmul_spectrum* sa, const uint64_t* b, size_t nb,
+                     const dmul_spectrum* sb, uint64_t* out, unsigned flags) {
+  if (!c || !sa || !out) return DMUL_EINVAL;
+  if (sb) {
+    if (b || nb != sb->na) return DMUL_EINVAL;
+  } else {
+    const int rc = check_args(nullptr, 0, b, nb, out);
+    if (rc) return rc;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  const int rc = enqueue_product(c, nullptr, sa->na, b, nb, out, flags, c->d_status, nullptr, sa, sb);
   if (rc == DMUL_EDEVICE && c->pending == DMUL_OK) c->pending = rc;
   return rc;
 }

@@ -71,14 +71,18 @@ int BatchEngine::reserve(dmul_ctx* ctx, size_t ws_words, size_t sync_words, size
 }
 
 int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, const size_t* na,
-                     const uint64_t* const* b, const size_t* nb, uint64_t* const* out,
-                     int32_t* status, unsigned flags, int* status_dev) {
+                     const dmul_spectrum* const* sa, const uint64_t* const* b, const size_t* nb,
+                     const dmul_spectrum* const* sb, uint64_t* const* out, int32_t* status,
+                     unsigned flags, int* status_dev) {
   if (!copied_) {
     if (hipEventCreateWithFlags(&copied_, hipEventDisableTiming) != hipSuccess) return DMUL_EDEVICE;
   }
-  // plan, and group the products by transform length
+  // plan, and group the products by transform length (and whether cached
+  // spectra stand in for operands: those never take the one-workgroup kernel)
   std::vector<PlanDev> plans(count);
-  std::map<uint64_t, std::vector<uint32_t>> classes;   // by transform length N
+  std::map<std::pair<uint64_t, int>, std::vector<uint32_t>> classes;
+  auto spec_a = [&](size_t i) { return sa ? sa[i] : nullptr; };
+  auto spec_b = [&](size_t i) { return sb ? sb[i] : nullptr; };
   size_t ws_words = 0, sync_words = 0, nvalid = 0;
   for (size_t i = 0; i < count; ++i) {
     if (na[i] == 0 || nb[i] == 0) {
@@ -86,12 +90,13 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       if (e != hipSuccess) return from_hip(e);
       continue;
     }
-    const int rc = make_plan(na[i], nb[i], flags & (DMUL_FLAG_K_MASK | DMUL_FLAG_POW2), &plans[i]);
+    const int rc = spectrum_plan(spec_a(i), na[i], spec_b(i), nb[i],
+                                 flags & (DMUL_FLAG_K_MASK | DMUL_FLAG_POW2), &plans[i]);
     if (rc) {
       status[i] = rc;
       continue;
     }
-    classes[plans[i].N].push_back((uint32_t)i);
+    classes[{plans[i].N, (spec_a(i) || spec_b(i)) ? 1 : 0}].push_back((uint32_t)i);
     ws_words += workspace_words(plans[i]);
     sync_words += recover_blocks(plans[i]) + 1;
     ++nvalid;
@@ -106,11 +111,11 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
   // the staging buffer may still feed the previous batch's copy
   if (hipEventSynchronize(copied_) != hipSuccess) return DMUL_EDEVICE;
   size_t wofs = 0, sofs = 0, di = 0;
-  struct Cls { PlanDev p0; size_t first, n; Shape sh; };
+  struct Cls { PlanDev p0; int spectra; size_t first, n; Shape sh; };
   std::vector<Cls> cls;
   for (auto& kv : classes) {
     const PlanDev& p0 = plans[kv.second[0]];
-    Cls c{p0, di, kv.second.size(), {}};
+    Cls c{p0, kv.first.second, di, kv.second.size(), {}};
     c.sh.logR = p0.logR;
     c.sh.logC = p0.logC;
     c.sh.rad3 = p0.rad3;
@@ -127,7 +132,11 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       d.status = status_dev + i;
       d.rec_sync = sync_ + sofs;
       d.nblk = (uint32_t)recover_blocks(plans[i]);
-      d.square = (a[i] == b[i] && na[i] == nb[i]) ? 1 : 0;
+      const dmul_spectrum* si = spec_a(i);
+      const dmul_spectrum* ti = spec_b(i);
+      d.square = (si || ti) ? (si == ti ? 1 : 0) : ((a[i] == b[i] && na[i] == nb[i]) ? 1 : 0);
+      d.xs = si ? si->dev : nullptr;
+      d.ys = ti ? ti->dev : nullptr;
       if (!d.square) c.sh.any_nonsquare = 1;
       c.sh.max_nblk = std::max(c.sh.max_nblk, d.nblk);
       wofs += workspace_words(plans[i]);
@@ -152,7 +161,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
     for (size_t i = 0; i < nvalid; ++i) {
       const ProdDesc& d = h_desc_[i];
       mix((uint64_t)d.a); mix((uint64_t)d.b); mix((uint64_t)d.out); mix(d.pl.na); mix(d.pl.nb);
-      mix((uint64_t)d.status); mix((uint64_t)d.ws);
+      mix((uint64_t)d.status); mix((uint64_t)d.ws); mix((uint64_t)d.xs); mix((uint64_t)d.ys);
     }
     auto it = graphs_.find(sig);
     if (it != graphs_.end()) {
@@ -191,7 +200,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       Work w{};
       w.many = descs + c.first + off;
       w.count = (uint32_t)std::min<size_t>(65535, c.n - off);
-      if (small_fits(c.p0)) {
+      if (!c.spectra && small_fits(c.p0)) {
         e = launch_small(w, c.sh, ctx->cs, tw, ctx->d_div, &ctx->h_div, ctx->stream, marks);
         continue;
       }

@@ -8,6 +8,8 @@
 #include <map>
 #include <vector>
 
+#include <dmul.h>
+
 #include "internal.hpp"
 
 struct dmul_ctx;
@@ -22,7 +24,8 @@ class BatchEngine {
   // Captured graphs bake in launch parameters: drop them when those change.
   void forget_graphs() { drop_graphs(); }
   int run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, const size_t* na,
-          const uint64_t* const* b, const size_t* nb, uint64_t* const* out, int32_t* status,
+          const dmul_spectrum* const* sa, const uint64_t* const* b, const size_t* nb,
+          const dmul_spectrum* const* sb, uint64_t* const* out, int32_t* status,
           unsigned flags, int* status_dev);
 
  private:

@@ -104,6 +104,15 @@ struct dmul_ctx {
   std::mutex mu;
 };
 
+// Cached forward transforms of one operand (both primes) for one plan.
+struct dmul_spectrum {
+  int device = 0;
+  size_t na = 0;                 // limbs of the operand
+  unsigned flags = 0;            // planning flags it was made with
+  dmi::PlanDev pl{};             // the plan (k, N, layout) it is valid for
+  uint64_t* dev = nullptr;       // 2N words: transform mod p1, then mod p2
+};
+
 namespace dmi {
 int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl);
 size_t workspace_words(const PlanDev& pl);
@@ -114,5 +123,8 @@ int row_iters_for(const dmul_ctx* ctx, const PlanDev& pl);
 bool size_class(uint64_t N, int* rad3, int* e);
 int from_hip(hipError_t e);
 int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
-                    uint64_t* out, unsigned flags, int* status, uint64_t* residues);
+                    uint64_t* out, unsigned flags, int* status, uint64_t* residues,
+                    const dmul_spectrum* sa = nullptr, const dmul_spectrum* sb = nullptr);
+int spectrum_plan(const dmul_spectrum* sa, size_t na, const dmul_spectrum* sb, size_t nb,
+                  unsigned flags, PlanDev* pl);
 }  // namespace dmi

@@ -97,7 +97,16 @@ struct ProdDesc {
   uint32_t* rec_sync;       // recovery: the carry map of each block (nblk words)
   uint32_t nblk;            // recovery workgroups
   int square;               // a == b: one operand transformed
+  const uint64_t* xs;       // cached forward transforms of a (2N words: mod p1, mod p2), or null
+  const uint64_t* ys;       // the same for b, or null
 };
+
+// Whether the forward passes transform operand op (0 = a, 1 = b) of d:
+// not a squared product's second operand, nor an operand with a cached
+// spectrum.
+__host__ __device__ inline bool transforms_operand(const ProdDesc& d, int op) {
+  return op == 0 ? d.xs == nullptr : (!d.square && d.ys == nullptr);
+}
 
 // A launch over products of one transform length: `one` when many is null,
 // else many[0 .. count) (device memory), one per blockIdx.z.

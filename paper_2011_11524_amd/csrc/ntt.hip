@@ -73,7 +73,7 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
   uint64_t* troots = lds + T * G::STRIDE;        // [prime][R/2]
   const ProdDesc d = load_desc(w);
   const int op = blockIdx.y;
-  if (op == 1 && d.square) return;               // a square transforms one operand
+  if (!transforms_operand(d, op)) return;         // squared product, or a cached spectrum
   const uint64_t* src = op ? d.b : d.a;
   const uint64_t nl = op ? d.pl.nb : d.pl.na;
   const uint64_t ng = op ? d.pl.m : d.pl.n;
@@ -183,11 +183,13 @@ k_rows(Work w, Consts cs, TwiddleSet tw) {
   extern __shared__ uint64_t lds[];
   const ProdDesc d = load_desc(w);
   const int y = blockIdx.y;
-  if (!INV && y >= 2 && d.square) return;
+  if (!INV && !transforms_operand(d, y >> 1)) return;
   const int pi = y & 1;
   const Prime P = cs.P[pi];
   uint64_t* X = d.ws + (size_t)y * d.pl.N;                       // inverse: y = prime
-  const uint64_t* Y = d.ws + (size_t)(d.square ? pi : 2 + pi) * d.pl.N;
+  // inverse: the two spectra, from the workspace or from cached transforms
+  const uint64_t* Xs = d.xs ? d.xs + (size_t)pi * d.pl.N : X;
+  const uint64_t* Y = d.square ? Xs : (d.ys ? d.ys + (size_t)pi * d.pl.N : d.ws + (size_t)(2 + pi) * d.pl.N);
   const uint64_t R = (uint64_t)(d.pl.rad3 ? 3 : 1) << d.pl.logR;  // rows of C points
   const uint32_t groups = (uint32_t)((R + RPW - 1) / RPW);
   const int r = threadIdx.x / NT, t = threadIdx.x % NT;
@@ -208,8 +210,8 @@ k_rows(Work w, Consts cs, TwiddleSet tw) {
     if (row < R) {
 #pragma unroll
       for (int j = 0; j < E; ++j) {
-        cur[j] = X[row * C + t + j * NT];
-        if (INV) cur[j] = mont_mul(cur[j], Y[row * C + t + j * NT], P);
+        if (INV) cur[j] = mont_mul(Xs[row * C + t + j * NT], Y[row * C + t + j * NT], P);
+        else cur[j] = X[row * C + t + j * NT];
       }
     } else {
 #pragma unroll
