@@ -15,16 +15,24 @@ Each request's latency is the time from its arrival to the host observing
 its batch complete (a HIP event on the engine's stream).  The loop is
 argument marshalling and bookkeeping only; every product runs in the
 library's kernels.
+
+Transforms can stay resident too: with a spectrum cache, an operand that
+comes back (the same pool slice, in a product of the same plan k and N)
+gets its forward transforms cached as a dmul spectrum, and later products
+with it skip those passes (dmul_batch_ex).  The cache is an LRU bounded in
+bytes; a spectrum made on one engine's stream is used on the other only
+after an event that orders the two.
 """
 from __future__ import annotations
 
 import ctypes
 import time
+from collections import OrderedDict
 from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Context, DmulError, lib, torch, workspace_bytes
+from . import Context, DmulError, lib, plan, spectrum_bytes, torch, workspace_bytes
 
 
 @dataclass
@@ -46,6 +54,8 @@ class ServeStats:
     latencies_s: list = field(default_factory=list)
     max_inflight_bytes: int = 0
     max_overlap: int = 0        # largest number of batches in flight at once
+    spectrum_hits: int = 0      # operands taken from cached transforms
+    spectra_made: int = 0
 
     def summary(self) -> dict:
         lat = np.asarray(self.latencies_s, dtype=float) * 1e3
@@ -60,6 +70,8 @@ class ServeStats:
             "mean_batch": self.completed / self.batches if self.batches else 0,
             "max_inflight_bytes": self.max_inflight_bytes,
             "max_batches_in_flight": self.max_overlap,
+            "spectrum_hits": self.spectrum_hits,
+            "spectra_made": self.spectra_made,
         }
 
 
@@ -83,15 +95,22 @@ class Server:
     engines: number of contexts/streams (>= 2 lets batches overlap).
     budget_bytes: device footprint one engine may hold in flight.
     max_batch: most requests per batch.
+    spectrum_cache_bytes: device memory for cached transforms of operands
+        that come back (0 = none).
     """
 
     def __init__(self, pool, device: int = 0, engines: int = 2, budget_bytes: int = 8 << 30,
-                 max_batch: int = 1024):
+                 max_batch: int = 1024, spectrum_cache_bytes: int = 0):
         self.pool = pool
         self.device = device
         self.engines = [_Engine(device, budget_bytes) for _ in range(max(1, engines))]
         self.max_batch = max_batch
         self._base = pool.data_ptr()
+        self.spec_cap = int(spectrum_cache_bytes)
+        self._spectra = OrderedDict()   # (offset, limbs, k, N) -> [Spectrum, bytes, event, stream]
+        self._spec_bytes = 0
+        self._seen = {}                 # operand key -> times used
+        self._stats = None
         lib()
 
     def close(self):
@@ -102,6 +121,35 @@ class Server:
     def footprint(na: int, nb: int) -> int:
         return workspace_bytes(na, nb) + 8 * (na + nb)
 
+    def _operand_spectrum(self, eng: _Engine, off: int, n: int, partner: int, pl):
+        """The cached transforms of pool[off: off + n] for plan pl, made now
+        (on eng's stream) if this operand has been used before; or None."""
+        if not self.spec_cap:
+            return None
+        key = (off, n, pl.k, pl.N)
+        ent = self._spectra.get(key)
+        if ent is not None:
+            self._spectra.move_to_end(key)
+            if ent[3] is not eng.stream:
+                eng.stream.wait_event(ent[2])
+            self._stats.spectrum_hits += 1
+            return ent[0]
+        seen = self._seen.get(key, 0)
+        self._seen[key] = seen + 1
+        nbytes = spectrum_bytes(n, partner)
+        if seen == 0 or nbytes > self.spec_cap:
+            return None
+        while self._spectra and self._spec_bytes + nbytes > self.spec_cap:
+            _, old = self._spectra.popitem(last=False)
+            self._spec_bytes -= old[1]
+        spec = eng.ctx.spectrum(self.pool[off: off + n], partner)
+        ev = torch.cuda.Event()
+        ev.record(eng.stream)
+        self._spectra[key] = [spec, nbytes, ev, eng.stream]
+        self._spec_bytes += nbytes
+        self._stats.spectra_made += 1
+        return spec
+
     def _launch(self, eng: _Engine, reqs: list, keep_outputs: bool):
         """Enqueue one batch: output buffer, dmul_batch, completion event."""
         total = sum(r.na + r.nb for r in reqs)
@@ -110,11 +158,14 @@ class Server:
         n = len(reqs)
         A = (ctypes.c_void_p * n)()
         B = (ctypes.c_void_p * n)()
+        SA = (ctypes.c_void_p * n)()
+        SB = (ctypes.c_void_p * n)()
         O = (ctypes.c_void_p * n)()
         NA = (ctypes.c_size_t * n)()
         NB = (ctypes.c_size_t * n)()
         st = (ctypes.c_int32 * n)()
         base, optr, ofs = self._base, out.data_ptr(), 0
+        used = []
         for i, r in enumerate(reqs):
             A[i] = base + 8 * r.a_off
             B[i] = base + 8 * r.b_off
@@ -122,13 +173,27 @@ class Server:
             NB[i] = r.nb
             O[i] = optr + 8 * ofs
             ofs += r.na + r.nb
-        rc = eng.ctx._lib.dmul_batch(eng.ctx._h, n, A, NA, B, NB, O, st, 0)
+            if self.spec_cap:
+                pl = plan(r.na, r.nb)
+                sa = self._operand_spectrum(eng, r.a_off, r.na, r.nb, pl)
+                sb = (sa if (r.b_off, r.nb) == (r.a_off, r.na)
+                      else self._operand_spectrum(eng, r.b_off, r.nb, r.na, pl))
+                if sa is not None:
+                    SA[i] = sa._h.value
+                    used.append(sa)
+                if sb is not None:
+                    SB[i] = sb._h.value
+                    used.append(sb)
+        if used:
+            rc = eng.ctx._lib.dmul_batch_ex(eng.ctx._h, n, A, NA, SA, B, NB, SB, O, st, 0)
+        else:
+            rc = eng.ctx._lib.dmul_batch(eng.ctx._h, n, A, NA, B, NB, O, st, 0)
         if rc:
             raise DmulError(rc, "dmul_batch")
         ev = torch.cuda.Event()
         ev.record(eng.stream)
         nbytes = sum(self.footprint(r.na, r.nb) for r in reqs)
-        eng.busy = (ev, reqs, out if keep_outputs else None, nbytes, (A, B, O, NA, NB, st))
+        eng.busy = (ev, reqs, out if keep_outputs else None, nbytes, (A, B, O, NA, NB, st, SA, SB, used))
 
     def _retire(self, eng: _Engine, t0: float, stats: ServeStats, results: dict | None):
         ev, reqs, out, nbytes, keep = eng.busy
@@ -156,6 +221,7 @@ class Server:
         available at once.  Returns the statistics and, with keep_outputs,
         {rid: result tensor}."""
         stats = ServeStats()
+        self._stats = stats
         results = {} if keep_outputs else None
         nxt = 0                      # next request not yet admitted
         t0 = time.perf_counter()

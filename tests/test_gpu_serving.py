@@ -78,3 +78,52 @@ def test_admission_respects_budget(env):
     biggest = max(serve.Server.footprint(r.na, r.nb) for r in reqs)
     assert stats.max_inflight_bytes <= 2 * max(budget, biggest)
     assert stats.batches > 2
+
+
+def test_spectrum_cache_reuses_hot_operands(env):
+    """Requests that come back to a few hot operands (and squares of them):
+    the server caches their transforms and later products skip those
+    passes; every result still equals the product alone, and a sample the
+    oracle."""
+    dm, serve, torch, pool_h, pool = env
+    _note("serving with a spectrum cache")
+    rng = np.random.default_rng(95)
+    npool = len(pool_h)
+    hot = []
+    for _ in range(6):
+        n = int(rng.integers(300, 3000))
+        hot.append((int(rng.integers(0, npool - n)), n))
+    reqs = []
+    for i in range(240):
+        u = rng.random()
+        if u < 0.1:
+            a_off, na = hot[int(rng.integers(0, len(hot)))]
+            b_off, nb = a_off, na                       # a square of a hot operand
+        else:
+            nb = int(rng.integers(50, 3000))
+            b_off = int(rng.integers(0, npool - nb))
+            if u < 0.7:
+                a_off, na = hot[int(rng.integers(0, len(hot)))]
+            else:
+                na = int(rng.integers(50, 3000))
+                a_off = int(rng.integers(0, npool - na))
+        reqs.append(serve.Request(i, a_off, na, b_off, nb, 0.0))
+    srv = serve.Server(pool, engines=2, budget_bytes=32 << 20, max_batch=32,
+                       spectrum_cache_bytes=256 << 20)
+    try:
+        stats, res = srv.run(reqs, keep_outputs=True, realtime=False)
+        torch.cuda.synchronize()
+    finally:
+        srv.close()
+    s = stats.summary()
+    assert s["requests"] == len(reqs)
+    assert s["spectra_made"] > 0 and s["spectrum_hits"] > 0, s
+    for r in reqs:
+        a = pool[r.a_off: r.a_off + r.na]
+        b = pool[r.b_off: r.b_off + r.nb]
+        alone = dm.mul(a, b)
+        assert torch.equal(res[r.rid], alone), f"request {r.rid} differs from the product alone"
+    for r in reqs[::40]:
+        a = pool_h[r.a_off: r.a_off + r.na]
+        b = pool_h[r.b_off: r.b_off + r.nb]
+        np.testing.assert_array_equal(dm.to_host(res[r.rid]), oracle.mul_ntt(a, b))
