@@ -242,6 +242,57 @@ def run_serving(dm, torch, count: int, seed: int = 5005):
     return out
 
 
+def run_serving_hot(dm, torch, count: int, hot_frac: float, seed: int = 5105, min_len: int = 1 << 19):
+    """Serving with operands that come back: the serving length mix, but a
+    fraction `hot_frac` of the requests multiply one of 32 hot operands by a
+    partner of 80..100% of its length (a resident operand reused with
+    similar-sized partners, so its plan repeats).  The same requests are
+    served back to back without and with the spectrum cache (cached
+    transforms of returning operands); a sample of results is compared
+    between the two runs."""
+    import numpy as np
+    import synth
+    from paper_2011_11524_amd import serve
+    pool_limbs = 1 << 21
+    pool_h = synth.pack_digits(np.random.default_rng(seed + 10).integers(0, 10, size=pool_limbs * 19,
+                                                                          dtype=np.uint8))
+    pool = dm.to_device(pool_h)
+    la, lb = synth.serving_lengths(count, seed=seed)
+    reqs = serve.make_requests(la, lb, np.zeros(count), pool_limbs, seed=seed + 1)
+    rng = np.random.default_rng(seed + 2)
+    hot = [reqs[int(i)] for i in rng.choice(count, size=32, replace=False)]
+    for i, r in enumerate(reqs):
+        if rng.random() < hot_frac:
+            h = hot[int(rng.integers(0, len(hot)))]
+            nb = max(1, int(h.na * rng.uniform(0.8, 1.0)))
+            b_off = int(rng.integers(0, pool_limbs - nb + 1))
+            reqs[i] = serve.Request(r.rid, h.a_off, h.na, b_off, nb, 0.0)
+    sample = [int(i) for i in rng.choice(count, size=min(100, count), replace=False)]
+    res = {}
+    for name, cache in (("no_cache", 0), ("spectrum_cache", 4 << 30)):
+        srv = serve.Server(pool, engines=2, budget_bytes=8 << 30, max_batch=2048,
+                           spectrum_cache_bytes=cache, spectrum_min_len=min_len)
+        try:
+            srv.run(reqs[: min(500, count)], realtime=False)          # warm-up
+            st, _ = srv.run(reqs, realtime=False)
+            _, outs = srv.run([reqs[i] for i in sample], keep_outputs=True, realtime=False)
+        finally:
+            srv.close()
+        s = st.summary()
+        res[name] = {"wall_s": s["wall_s"], "digits_per_s": s["digits_per_s"],
+                     "spectrum_hits": s["spectrum_hits"], "spectra_made": s["spectra_made"],
+                     "_outs": outs}
+    same = all(torch.equal(res["no_cache"]["_outs"][k], res["spectrum_cache"]["_outs"][k])
+               for k in res["no_cache"]["_outs"])
+    for v in res.values():
+        v.pop("_outs")
+    res.update({"requests": count, "hot_fraction": hot_frac, "hot_operands": len(hot),
+                "spectrum_min_len": min_len,
+                "speedup": res["no_cache"]["wall_s"] / res["spectrum_cache"]["wall_s"],
+                "cached_vs_plain": "identical" if same else "DIFFERENT"})
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -254,6 +305,9 @@ def main() -> int:
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--serving", action="store_true", help="also run the serving workload")
     ap.add_argument("--requests", type=int, default=100_000)
+    ap.add_argument("--serving-hot", type=float, default=0.0,
+                    help="also serve a mix where this fraction of requests reuses 32 hot operands, "
+                         "without and with the spectrum cache")
     ap.add_argument("--pow2", action="store_true",
                     help="power-of-two transform length even where 3*2^e is shorter")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -363,6 +417,9 @@ def main() -> int:
     if args.serving:
         result["serving"] = run_serving(dm, torch, args.requests)
         print(f"[bench] serving: {json.dumps(result['serving'])}", flush=True)
+    if args.serving_hot > 0:
+        result["serving_hot"] = run_serving_hot(dm, torch, min(args.requests, 4000), args.serving_hot)
+        print(f"[bench] serving_hot: {json.dumps(result['serving_hot'])}", flush=True)
 
     if not args.no_cpu_baseline:
         want, times = cpu_baseline(a, b, args.cpu_budget, 3)

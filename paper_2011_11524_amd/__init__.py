@@ -109,7 +109,7 @@ def lib():
     L.dmul_ctx_profile_events.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     L.dmul_ctx_tune.argtypes = [vp, ctypes.c_uint64, ctypes.c_int]
-    L.dmul_spectrum_create.argtypes = [vp, vp, sz, sz, ctypes.c_uint, ctypes.POINTER(vp)]
+    L.dmul_spectrum_create.argtypes = [vp, vp, sz, sz, ctypes.c_uint, vp, sz, ctypes.POINTER(vp)]
     L.dmul_spectrum_destroy.argtypes = [vp]
     L.dmul_spectrum_bytes.argtypes = [sz, sz, ctypes.c_uint]
     L.dmul_spectrum_bytes.restype = sz
@@ -162,12 +162,13 @@ class Spectrum:
     """Cached forward transforms of one operand (dmul_spectrum): made by
     Context.spectrum, used in place of the operand's limbs."""
 
-    def __init__(self, handle, na: int, nb_plan: int, flags: int, owner):
+    def __init__(self, handle, na: int, nb_plan: int, flags: int, owner, mem=None):
         self._h = handle
         self.na = int(na)
         self.nb_plan = int(nb_plan)
         self.flags = int(flags)
         self._lib = owner._lib
+        self.mem = mem          # the caller's buffer holding the transforms, if any
 
     def close(self) -> None:
         if getattr(self, "_h", None):
@@ -252,17 +253,21 @@ class Context:
         return out
 
     # -- cached transforms ---------------------------------------------------
-    def spectrum(self, a, nb: int, force_k: int = 0, pow2: bool = False) -> "Spectrum":
+    def spectrum(self, a, nb: int, force_k: int = 0, pow2: bool = False, mem=None) -> "Spectrum":
         """Forward transforms of a for products with partners of nb limbs
-        (valid for every partner with the same plan k and N)."""
+        (valid for every partner with the same plan k and N).  mem: an
+        optional device tensor (spectrum_bytes(...) bytes at least) that
+        holds them; the Spectrum keeps a reference to it."""
         _check_limbs(a, "a")
         h = ctypes.c_void_p()
         flags = flags_for(force_k, pow2)
+        mp = ctypes.c_void_p(mem.data_ptr()) if mem is not None else None
+        mb = mem.numel() * mem.element_size() if mem is not None else 0
         rc = self._lib.dmul_spectrum_create(self._h, ctypes.c_void_p(a.data_ptr()), a.numel(), int(nb),
-                                            flags, ctypes.byref(h))
+                                            flags, mp, mb, ctypes.byref(h))
         if rc:
             raise DmulError(rc, "dmul_spectrum_create")
-        return Spectrum(h, a.numel(), nb, flags, self)
+        return Spectrum(h, a.numel(), nb, flags, self, mem)
 
     def mul_spectrum_async(self, sa: "Spectrum", b, out, sb: "Spectrum" = None, force_k: int = 0,
                            pow2: bool = False) -> None:

@@ -767,13 +767,15 @@ size_t dmul_spectrum_bytes(size_t na, size_t nb, unsigned flags) {
 }
 
 int dmul_spectrum_create(dmul_ctx* c, const uint64_t* a, size_t na, size_t nb, unsigned flags,
-                         dmul_spectrum** out) {
+                         void* mem, size_t mem_bytes, dmul_spectrum** out) {
   if (!c || !out) return DMUL_EINVAL;
   *out = nullptr;
   if (!a || na == 0 || nb == 0) return DMUL_EINVAL;
   PlanDev pl;
   int rc = make_plan(na, nb, flags, &pl);
   if (rc) return rc;
+  const size_t bytes = 2 * (size_t)pl.N * sizeof(uint64_t);
+  if (mem && (mem_bytes < bytes || ((uintptr_t)mem & 7))) return DMUL_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
   TwiddleSet tw;
   rc = get_twiddles(c, pl, &tw);
@@ -784,7 +786,13 @@ int dmul_spectrum_create(dmul_ctx* c, const uint64_t* a, size_t na, size_t nb, u
   s->na = na;
   s->flags = flags;
   s->pl = pl;
-  hipError_t e = hipMalloc(&s->dev, 2 * (size_t)pl.N * sizeof(uint64_t));
+  hipError_t e = hipSuccess;
+  if (mem) {
+    s->dev = (uint64_t*)mem;
+  } else {
+    e = hipMalloc(&s->dev, bytes);
+    s->owned = true;
+  }
   if (e != hipSuccess) {
     delete s;
     return from_hip(e);
@@ -803,7 +811,7 @@ int dmul_spectrum_create(dmul_ctx* c, const uint64_t* a, size_t na, size_t nb, u
   const Shape sh{pl.logR, pl.logC, pl.rad3, 0, row_iters_for(c, pl), 0};
   e = launch_forward(w, sh, c->cs, tw, c->d_div, c->stream, nullptr);
   if (e != hipSuccess) {
-    (void)hipFree(s->dev);
+    if (s->owned) (void)hipFree(s->dev);
     delete s;
     if (c->pending == DMUL_OK) c->pending = DMUL_EDEVICE;
     return from_hip(e);
@@ -814,7 +822,7 @@ int dmul_spectrum_create(dmul_ctx* c, const uint64_t* a, size_t na, size_t nb, u
 
 int dmul_spectrum_destroy(dmul_spectrum* s) {
   if (!s) return DMUL_EINVAL;
-  if (s->dev) (void)hipFree(s->dev);
+  if (s->dev && s->owned) (void)hipFree(s->dev);
   delete s;
   return DMUL_OK;
 }

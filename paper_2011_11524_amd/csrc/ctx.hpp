@@ -111,6 +111,7 @@ struct dmul_spectrum {
   unsigned flags = 0;            // planning flags it was made with
   dmi::PlanDev pl{};             // the plan (k, N, layout) it is valid for
   uint64_t* dev = nullptr;       // 2N words: transform mod p1, then mod p2
+  bool owned = false;            // dev is the library's allocation
 };
 
 namespace dmi {

@@ -97,16 +97,20 @@ class Server:
     max_batch: most requests per batch.
     spectrum_cache_bytes: device memory for cached transforms of operands
         that come back (0 = none).
+    spectrum_min_len: the shortest transform length worth caching: making a
+        spectrum costs host work and two launches of its own, which pays off
+        only where a forward transform is long.
     """
 
     def __init__(self, pool, device: int = 0, engines: int = 2, budget_bytes: int = 8 << 30,
-                 max_batch: int = 1024, spectrum_cache_bytes: int = 0):
+                 max_batch: int = 1024, spectrum_cache_bytes: int = 0, spectrum_min_len: int = 1 << 19):
         self.pool = pool
         self.device = device
         self.engines = [_Engine(device, budget_bytes) for _ in range(max(1, engines))]
         self.max_batch = max_batch
         self._base = pool.data_ptr()
         self.spec_cap = int(spectrum_cache_bytes)
+        self.spec_min = int(spectrum_min_len)
         self._spectra = OrderedDict()   # (offset, limbs, k, N) -> [Spectrum, bytes, event, stream]
         self._spec_bytes = 0
         self._seen = {}                 # operand key -> times used
@@ -124,7 +128,7 @@ class Server:
     def _operand_spectrum(self, eng: _Engine, off: int, n: int, partner: int, pl):
         """The cached transforms of pool[off: off + n] for plan pl, made now
         (on eng's stream) if this operand has been used before; or None."""
-        if not self.spec_cap:
+        if not self.spec_cap or pl.N < self.spec_min:
             return None
         key = (off, n, pl.k, pl.N)
         ent = self._spectra.get(key)
@@ -132,6 +136,7 @@ class Server:
             self._spectra.move_to_end(key)
             if ent[3] is not eng.stream:
                 eng.stream.wait_event(ent[2])
+                ent[0].mem.record_stream(eng.stream)
             self._stats.spectrum_hits += 1
             return ent[0]
         seen = self._seen.get(key, 0)
@@ -142,7 +147,9 @@ class Server:
         while self._spectra and self._spec_bytes + nbytes > self.spec_cap:
             _, old = self._spectra.popitem(last=False)
             self._spec_bytes -= old[1]
-        spec = eng.ctx.spectrum(self.pool[off: off + n], partner)
+        with torch.cuda.stream(eng.stream):      # from torch's caching allocator, no hipMalloc
+            mem = torch.empty(nbytes // 8, dtype=torch.uint64, device=f"cuda:{self.device}")
+        spec = eng.ctx.spectrum(self.pool[off: off + n], partner, mem=mem)
         ev = torch.cuda.Event()
         ev.record(eng.stream)
         self._spectra[key] = [spec, nbytes, ev, eng.stream]

@@ -109,7 +109,7 @@ def test_spectrum_cache_reuses_hot_operands(env):
                 a_off = int(rng.integers(0, npool - na))
         reqs.append(serve.Request(i, a_off, na, b_off, nb, 0.0))
     srv = serve.Server(pool, engines=2, budget_bytes=32 << 20, max_batch=32,
-                       spectrum_cache_bytes=256 << 20)
+                       spectrum_cache_bytes=256 << 20, spectrum_min_len=0)
     try:
         stats, res = srv.run(reqs, keep_outputs=True, realtime=False)
         torch.cuda.synchronize()

@@ -152,3 +152,24 @@ def test_batch_with_spectra(dm, ctx):
         np.testing.assert_array_equal(dm.to_host(o), w)
     for s in keep:
         s.close()
+
+
+def test_spectrum_in_caller_memory(dm, ctx):
+    """Transforms held in a buffer the caller allocated (a torch tensor):
+    same products; a buffer too small is refused."""
+    import torch
+    rng = np.random.default_rng(515)
+    na, nb = 3000, 2500
+    a, b = _limbs(rng, na), _limbs(rng, nb)
+    da, db = dm.to_device(a), dm.to_device(b)
+    _note("spectrum in caller memory")
+    words = dm.spectrum_bytes(na, nb) // 8
+    mem = torch.empty(words, dtype=torch.uint64, device="cuda")
+    sa = ctx.spectrum(da, nb, mem=mem)
+    got = dm.to_host(ctx.mul_spectrum(sa, db))
+    np.testing.assert_array_equal(got, oracle.mul_ntt(a, b))
+    sa.close()
+    small = torch.empty(words - 1, dtype=torch.uint64, device="cuda")
+    with pytest.raises(dm.DmulError) as e:
+        ctx.spectrum(da, nb, mem=small)
+    assert e.value.code == dm.DMUL_EINVAL
