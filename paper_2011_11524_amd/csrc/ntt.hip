@@ -359,8 +359,11 @@ constexpr int cols_per_tile(int logl) { return cols_for(logl, 1024, (1 << logl) 
 constexpr int fwd_triples_per_tile(int logl) { return triples_for(logl, 768, 1 << logl); }
 constexpr int triples_per_tile(int logl) { return triples_for(logl, 1024, (1 << logl) / 2); }
 constexpr uint64_t kRowMinGroups = 1024;
+// Points per thread (log2) and rows per workgroup in the row passes.
+constexpr int row_loge(int logl) { return loge_for(logl); }
+constexpr int kRowThreads = 256;
 constexpr int rows_per_wg(int logl) {
-  return (256 >> (logl - loge_for(logl))) < 1 ? 1 : (256 >> (logl - loge_for(logl)));
+  return (kRowThreads >> (logl - row_loge(logl))) < 1 ? 1 : (kRowThreads >> (logl - row_loge(logl)));
 }
 
 template <typename K>
@@ -402,7 +405,7 @@ static hipError_t fwd_cols_l(const Work& w, const Shape& sh, const Consts& cs, c
 template <int LOGC, bool INV>
 static hipError_t rows_l(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                          hipStream_t st) {
-  constexpr int LOGE = loge_for(LOGC), RPW = rows_per_wg(LOGC);
+  constexpr int LOGE = row_loge(LOGC), RPW = rows_per_wg(LOGC);
   using G = Geometry<LOGC, LOGE>;
   const size_t lds = ((size_t)RPW * G::STRIDE + (size_t)G::L / 2) * sizeof(uint64_t);
   auto kern = k_rows<LOGC, LOGE, RPW, INV, true>;

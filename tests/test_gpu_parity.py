@@ -434,3 +434,46 @@ def test_batch_graph_replays_match(dm):
             np.testing.assert_array_equal(dm.to_host(ctx.mul(x, x)), oracle.mul_ntt(dm.to_host(x), dm.to_host(x)))
     finally:
         ctx.close()
+
+
+def test_context_budget_enomem(dm):
+    """A context's workspace budget: a product needing more gets DMUL_ENOMEM
+    (single product) or that status per product (batch); products within it
+    still run."""
+    _note("workspace budget")
+    c = dm.Context(0, budget_bytes=1 << 20)
+    try:
+        rng = np.random.default_rng(31)
+        big_a = rng.integers(0, 10 ** 19, size=30000, dtype=np.uint64)   # N = 2^16: 2 MiB workspace
+        big_b = rng.integers(0, 10 ** 19, size=30000, dtype=np.uint64)
+        assert dm.workspace_bytes(30000, 30000) > (1 << 20)
+        with pytest.raises(dm.DmulError) as e:
+            c.mul(dm.to_device(big_a), dm.to_device(big_b))
+        assert e.value.code == dm.DMUL_ENOMEM
+        a = rng.integers(0, 10 ** 19, size=3000, dtype=np.uint64)
+        b = rng.integers(0, 10 ** 19, size=2000, dtype=np.uint64)
+        assert dm.workspace_bytes(3000, 2000) <= (1 << 20)
+        np.testing.assert_array_equal(dm.to_host(c.mul(dm.to_device(a), dm.to_device(b))),
+                                      oracle.mul_ntt(a, b))
+        outs, st = c.batch([(dm.to_device(big_a), dm.to_device(big_b))])
+        assert st == [dm.DMUL_ENOMEM]
+    finally:
+        c.close()
+
+
+def test_largest_power_of_two_length(dm, ctx):
+    """The longest transform, N = 2^26 (8192 x 8192, two 3*10^8-digit
+    operands at k = 15): the product's residues modulo 10^19 - 1 and
+    10^19 + 1, exact at any size, and the digit range."""
+    na = nb = 15_800_000
+    pl = dm.plan(na, nb)
+    assert (pl.N, pl.factor, pl.log2_rows, pl.log2_cols) == (1 << 26, 1, 13, 13)
+    _note(f"N=2^26 {na}x{nb} limbs, k={pl.k}")
+    rng = np.random.default_rng(2626)
+    a = rng.integers(0, 10 ** 19, size=na, dtype=np.uint64)
+    b = rng.integers(0, 10 ** 19, size=nb, dtype=np.uint64)
+    got = _gpu_mul(dm, ctx, a, b)
+    assert int(got.max()) < 10 ** 19
+    (a1, a2), (b1, b2), (z1, z2) = _mod_pm(a), _mod_pm(b), _mod_pm(got)
+    assert z1 == a1 * b1 % (10 ** 19 - 1)
+    assert z2 == a2 * b2 % (10 ** 19 + 1)
