@@ -121,11 +121,15 @@ k_rec_scan(Work w, RecTable rt) {
   }
 }
 
-// Pass 2: z_i = (s_i + carry_i) mod B from the workgroup's incoming carry and
-// a scan of its maps, then the base-10^19 limbs whose first digit lies in
-// the workgroup's digit range (digits of the two positions after it are
-// included: a limb may end there).
-template <int PT>
+// Pass 2: z_i = (s_i + carry_i) mod B from the block's incoming carry and a
+// scan of its maps, then the base-10^19 limbs whose first digit lies in the
+// block's digit range (digits of the two positions after it are included: a
+// limb may end there).  The incoming carry comes from k_rec_scan, or with
+// PREFIX (products of at most kPrefixBlocks blocks) from composing the maps
+// of all earlier blocks here, which saves the scan launch.
+constexpr uint32_t kPrefixBlocks = 2048;
+
+template <int PT, bool PREFIX>
 __global__ void __launch_bounds__(kRecThreads)
 k_rec_apply(Work w, RecTable rt, const DivTable* __restrict__ dt_g) {
   constexpr int BLK = kRecThreads * PT;
@@ -152,9 +156,25 @@ k_rec_apply(Work w, RecTable rt, const DivTable* __restrict__ dt_g) {
       s[u] = i < rc.NP ? s_in[i] : 0;
       if (i < rc.NP) f = compose(carry_map(s[u], B), f);
     }
+    uint32_t cin;
+    if constexpr (PREFIX) {
+      // maps of blocks 0 .. blk-1 in order: runs per thread, then a scan
+      const uint32_t* __restrict__ maps = d.rec_sync;
+      const uint32_t per = (blk + kRecThreads - 1) / kRecThreads;
+      const uint32_t lo = threadIdx.x * per < blk ? threadIdx.x * per : blk;
+      const uint32_t hi = lo + per < blk ? lo + per : blk;
+      uint32_t g = kIdentityMap;
+      for (uint32_t b = lo; b < hi; ++b) g = compose(maps[b], g);
+      uint32_t all;
+      block_exclusive_scan(g, &all);
+      cin = apply_map(all, 0);
+      __syncthreads();   // the scan's shared words are used again below
+    } else {
+      cin = cins[blk];
+    }
     uint32_t total;
     const uint32_t before = block_exclusive_scan(f, &total);
-    uint32_t c = apply_map(before, cins[blk]);
+    uint32_t c = apply_map(before, cin);
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
       uint64_t t = s[u] + c;
@@ -255,10 +275,14 @@ hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, cons
                           const DivTable* dt_host, hipStream_t st, Marks* marks) {
   const RecTable rt = make_rec_table(cs, dt_host);
   const unsigned g = recover_grid(sh.max_nblk);
+  const bool prefix = sh.max_nblk <= kPrefixBlocks;
   hipLaunchKernelGGL(k_rec_crt<kRecPT>, dim3(g, 1, w.count), dim3(kRecThreads), 0, st, w, rt);
-  hipLaunchKernelGGL(k_rec_scan, dim3(1, 1, w.count), dim3(kScanThreads), 0, st, w, rt);
+  if (!prefix) hipLaunchKernelGGL(k_rec_scan, dim3(1, 1, w.count), dim3(kScanThreads), 0, st, w, rt);
   if (marks) marks->mark(kRecCrt, st);
-  hipLaunchKernelGGL(k_rec_apply<kRecPT>, dim3(g, 1, w.count), dim3(kRecThreads), 0, st, w, rt, dt);
+  if (prefix)
+    hipLaunchKernelGGL((k_rec_apply<kRecPT, true>), dim3(g, 1, w.count), dim3(kRecThreads), 0, st, w, rt, dt);
+  else
+    hipLaunchKernelGGL((k_rec_apply<kRecPT, false>), dim3(g, 1, w.count), dim3(kRecThreads), 0, st, w, rt, dt);
   if (marks) marks->mark(kRecApply, st);
   return hipGetLastError();
 }
