@@ -375,7 +375,7 @@ int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t*
   Shape sh{pl.logR, pl.logC, pl.rad3, d.square ? 0 : 1, row_iters_for(ctx, pl), d.nblk};
   Marks* marks = ctx->prof;
   if (ctx->prof) ctx->prof->begin(ctx->stream);
-  if (!residues && !sa && !sb && small_fits(pl))
+  if (!residues && !sa && !sb && small_fits(pl, 1))
     return from_hip(launch_small(w, sh, ctx->cs, tw, ctx->d_div, &ctx->h_div, ctx->stream, marks));
   hipError_t e = launch_forward(w, sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
   if (e == hipSuccess) e = launch_inverse(w, sh, ctx->cs, tw, ctx->stream, marks);

@@ -200,7 +200,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       Work w{};
       w.many = descs + c.first + off;
       w.count = (uint32_t)std::min<size_t>(65535, c.n - off);
-      if (!c.spectra && small_fits(c.p0)) {
+      if (!c.spectra && small_fits(c.p0, c.n)) {
         e = launch_small(w, c.sh, ctx->cs, tw, ctx->d_div, &ctx->h_div, ctx->stream, marks);
         continue;
       }

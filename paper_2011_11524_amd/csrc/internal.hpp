@@ -14,6 +14,8 @@ constexpr int kMaxLogC3 = 11;      // rows of 3 * 2^logC points: logC <= 11
 constexpr int kMaxLogR3 = 12;      // with C = 3M a column tile holds three columns of 2^logR points
 constexpr int kMinLogN3 = 4;       // lengths 3 * 2^e are used for e >= 4
 constexpr uint64_t kSmallMaxN = 4096;   // whole product in one workgroup up to this length
+constexpr uint64_t kSmallSoloMaxN = 2048;  // ... for a lone product (one workgroup vs the device)
+constexpr size_t kSmallMinCount = 8;       // products of a class that make 4096 worth it
 constexpr int kMinK = 13;          // p1*p2 < 10^(3k): three base-10^k parts per coefficient
 constexpr uint64_t kLimbBase = 10000000000000000000ULL;  // 10^19
 
@@ -132,8 +134,11 @@ hipError_t launch_inverse(const Work& w, const Shape& sh, const Consts& cs, cons
                           hipStream_t stream, Marks* marks);
 hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, const DivTable* dt,
                           const DivTable* dt_host, hipStream_t stream, Marks* marks);
-// Whole products in one workgroup (small.hip), for N <= kSmallMaxN.
-bool small_fits(const PlanDev& pl);
+// Whole products in one workgroup (small.hip): for N <= kSmallMaxN when a
+// launch carries at least kSmallMinCount products of the length, else for
+// N <= kSmallSoloMaxN (beyond it a lone product is faster on the passes,
+// which use the whole device).
+bool small_fits(const PlanDev& pl, size_t count);
 hipError_t launch_small(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                         const DivTable* dt, const DivTable* dt_host, hipStream_t stream, Marks* marks);
 size_t recover_blocks(const PlanDev& pl);

@@ -1,4 +1,5 @@
-// Whole products in one workgroup, for short transforms (N <= kSmallMaxN).
+// Whole products in one workgroup, for short transforms (N <= kSmallMaxN in
+// launches of at least kSmallMinCount products, N <= kSmallSoloMaxN else).
 //
 // A product whose transform fits the LDS of one workgroup runs every step
 // of the method in one kernel: digit-group split (Section 3.2), for each
@@ -189,7 +190,9 @@ static hipError_t small_launch(const Work& w, const Consts& cs, const TwiddleSet
   return hipGetLastError();
 }
 
-bool small_fits(const PlanDev& pl) { return pl.N <= (uint64_t)kSmallMaxN; }
+bool small_fits(const PlanDev& pl, size_t count) {
+  return pl.N <= (count >= kSmallMinCount ? kSmallMaxN : kSmallSoloMaxN);
+}
 
 hipError_t launch_small(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                         const DivTable* dt, const DivTable* dt_host, hipStream_t st, Marks* marks) {

@@ -195,30 +195,27 @@ def _sizes_at_most(dm, N, seed):
 
 
 def test_whole_product_kernel_every_class(dm, ctx):
-    """Every transform length of the one-workgroup kernel (N <= 4096), each
-    as a single product and as one batch of all of them, products and
-    squares, against the oracle."""
-    import torch
+    """Every transform length of the one-workgroup kernel (N <= 4096):
+    single products (that kernel up to N = 2048, the passes beyond), and
+    one batch with 8 products of every length (4 products, 4 squares), where
+    every length takes the kernel; all against the oracle."""
     rng = np.random.default_rng(9100)
-    cases = []
-    for N in _small_classes():
-        na, nb = _sizes_at_most(dm, N, N)
-        a = rng.integers(0, 10 ** 19, size=na, dtype=np.uint64)
-        b = rng.integers(0, 10 ** 19, size=nb, dtype=np.uint64)
-        cases.append((N, a, b))
     pairs, want = [], []
-    for N, a, b in cases:
-        _note(f"whole-product N={N} {len(a)}x{len(b)}")
-        w = oracle.mul_ntt(a, b)
-        np.testing.assert_array_equal(_gpu_mul(dm, ctx, a, b), w)
-        da, db = dm.to_device(a), dm.to_device(b)
-        pairs.append((da, db))
-        want.append(w)
-        sq = _gpu_mul(dm, ctx, a, a)
-        np.testing.assert_array_equal(sq, oracle.mul_ntt(a, a))
-        pairs.append((da, da))
-        want.append(sq)
-    _note("whole-product batch")
+    for N in _small_classes():
+        for rep in range(4):
+            na, nb = _sizes_at_most(dm, N, N + 1000 * rep)
+            a = rng.integers(0, 10 ** 19, size=na, dtype=np.uint64)
+            b = rng.integers(0, 10 ** 19, size=nb, dtype=np.uint64)
+            w = oracle.mul_ntt(a, b)
+            w2 = oracle.mul_ntt(a, a)
+            if rep == 0:
+                _note(f"whole-product N={N} {na}x{nb}")
+                np.testing.assert_array_equal(_gpu_mul(dm, ctx, a, b), w)
+                np.testing.assert_array_equal(_gpu_mul(dm, ctx, a, a), w2)
+            da, db = dm.to_device(a), dm.to_device(b)
+            pairs += [(da, db), (da, da)]
+            want += [w, w2]
+    _note(f"whole-product batch of {len(pairs)}")
     outs, st = ctx.batch(pairs)
     assert st == [0] * len(pairs)
     for o, w in zip(outs, want):
