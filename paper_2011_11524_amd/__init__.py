@@ -296,6 +296,25 @@ class Context:
         return out
 
     # -- batches -------------------------------------------------------------
+    def prepare_batch(self, pairs: Sequence, outs: Sequence) -> "PreparedBatch":
+        """Marshal a batch once, for submitting the same products again
+        (run_prepared): the pointer arrays are built here, not per call."""
+        return PreparedBatch(pairs, outs)
+
+    def run_prepared(self, pb: "PreparedBatch", force_k: int = 0, graph: bool = False,
+                     pow2: bool = False):
+        """Enqueue a prepared batch; returns its host status array (filled by
+        sync())."""
+        flags = flags_for(force_k, pow2) | (DMUL_FLAG_GRAPH if graph else 0)
+        if pb.spectra:
+            rc = self._lib.dmul_batch_ex(self._h, pb.n, pb.A, pb.NA, pb.SA, pb.B, pb.NB, pb.SB, pb.O,
+                                         pb.st, flags)
+        else:
+            rc = self._lib.dmul_batch(self._h, pb.n, pb.A, pb.NA, pb.B, pb.NB, pb.O, pb.st, flags)
+        if rc:
+            raise DmulError(rc, "dmul_batch")
+        return pb.st
+
     def batch_async(self, pairs: Sequence, outs: Sequence, force_k: int = 0, graph: bool = False,
                     pow2: bool = False):
         """Enqueue len(pairs) products (a_i, b_i) -> outs[i]; returns the host
@@ -303,34 +322,9 @@ class Context:
         this context's device instead of a tensor.  graph=True captures the
         batch in a HIP graph, replayed when the same batch is submitted
         again."""
-        n = len(pairs)
-        A = (ctypes.c_void_p * n)()
-        B = (ctypes.c_void_p * n)()
-        SA = (ctypes.c_void_p * n)()
-        SB = (ctypes.c_void_p * n)()
-        O = (ctypes.c_void_p * n)()
-        NA = (ctypes.c_size_t * n)()
-        NB = (ctypes.c_size_t * n)()
-        st = (ctypes.c_int32 * n)()
-        spectra = False
-        for i, ((a, b), o) in enumerate(zip(pairs, outs)):
-            for x, P, S, L in ((a, A, SA, NA), (b, B, SB, NB)):
-                if isinstance(x, Spectrum):
-                    S[i] = x._h.value
-                    L[i] = x.na
-                    spectra = True
-                else:
-                    P[i] = x.data_ptr() if x.numel() else 0
-                    L[i] = x.numel()
-            O[i] = o.data_ptr() if o.numel() else 0
-        flags = flags_for(force_k, pow2) | (DMUL_FLAG_GRAPH if graph else 0)
-        if spectra:
-            rc = self._lib.dmul_batch_ex(self._h, n, A, NA, SA, B, NB, SB, O, st, flags)
-        else:
-            rc = self._lib.dmul_batch(self._h, n, A, NA, B, NB, O, st, flags)
-        if rc:
-            raise DmulError(rc, "dmul_batch")
-        self._keep = (A, B, SA, SB, O, NA, NB)
+        pb = PreparedBatch(pairs, outs)
+        st = self.run_prepared(pb, force_k, graph, pow2)
+        self._keep = pb
         return st
 
     def batch(self, pairs: Sequence, force_k: int = 0, graph: bool = False, outs=None,
@@ -427,6 +421,35 @@ def mul_host(a, b, force_k: int = 0, device: int = 0, pow2: bool = False) -> np.
     if rc:
         raise DmulError(rc, "dmul_host")
     return out
+
+
+class PreparedBatch:
+    """The marshalled arguments of one batch (host arrays of device
+    pointers, sizes, spectra, statuses); keeps its tensors alive."""
+
+    def __init__(self, pairs: Sequence, outs: Sequence):
+        n = len(pairs)
+        self.n = n
+        self.A = (ctypes.c_void_p * n)()
+        self.B = (ctypes.c_void_p * n)()
+        self.SA = (ctypes.c_void_p * n)()
+        self.SB = (ctypes.c_void_p * n)()
+        self.O = (ctypes.c_void_p * n)()
+        self.NA = (ctypes.c_size_t * n)()
+        self.NB = (ctypes.c_size_t * n)()
+        self.st = (ctypes.c_int32 * n)()
+        self.spectra = False
+        self._refs = (list(pairs), list(outs))
+        for i, ((a, b), o) in enumerate(zip(pairs, outs)):
+            for x, P, S, L in ((a, self.A, self.SA, self.NA), (b, self.B, self.SB, self.NB)):
+                if isinstance(x, Spectrum):
+                    S[i] = x._h.value
+                    L[i] = x.na
+                    self.spectra = True
+                else:
+                    P[i] = x.data_ptr() if x.numel() else 0
+                    L[i] = x.numel()
+            self.O[i] = o.data_ptr() if o.numel() else 0
 
 
 _contexts: dict[int, Context] = {}

@@ -126,7 +126,20 @@ int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl) {
   if (fk && (fk < kMinK || fk > 18)) return DMUL_EINVAL;
   if (na == 0 || nb == 0) return DMUL_EINVAL;
   if (na > ((size_t)1 << 40) || nb > ((size_t)1 << 40)) return DMUL_ERANGE;
-  const u128 P = (u128)kP[0] * kP[1];
+  // largest group count allowed per k: (10^k - 1)^2 * min < p1*p2
+  static const struct Limits {
+    uint64_t lim[19];
+    Limits() {
+      const u128 P = (u128)kP[0] * kP[1];
+      uint64_t B1 = 1;
+      for (int kk = 0; kk <= 18; ++kk) {
+        const u128 L = (u128)(B1 - 1) * (B1 - 1);
+        const u128 q = kk ? (P - 1) / L : ~(u128)0;
+        lim[kk] = q > ~(u128)0 >> 64 ? ~0ULL : (uint64_t)q;
+        B1 *= 10;
+      }
+    }
+  } limits;
   int k = 0;
   uint64_t nk = 0, mk = 0;
   for (int kk = 18; kk >= kMinK; --kk) {
@@ -134,11 +147,7 @@ int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl) {
     const uint64_t a = (19 * (uint64_t)na + kk - 1) / kk;
     const uint64_t b = (19 * (uint64_t)nb + kk - 1) / kk;
     const uint64_t mn = a < b ? a : b;
-    uint64_t B1 = 1;
-    for (int i = 0; i < kk; ++i) B1 *= 10;
-    B1 -= 1;
-    const u128 L = (u128)B1 * B1;
-    if (L <= (P - 1) / mn) { k = kk; nk = a; mk = b; break; }
+    if (mn <= limits.lim[kk]) { k = kk; nk = a; mk = b; break; }
   }
   if (!k) return DMUL_ERANGE;
   // Transform length: the shortest 2^e or 3*2^e (Section 7.8) holding all

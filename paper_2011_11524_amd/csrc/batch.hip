@@ -77,12 +77,42 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
   if (!copied_) {
     if (hipEventCreateWithFlags(&copied_, hipEventDisableTiming) != hipSuccess) return DMUL_EDEVICE;
   }
+  auto spec_a = [&](size_t i) { return sa ? sa[i] : nullptr; };
+  auto spec_b = [&](size_t i) { return sb ? sb[i] : nullptr; };
+  // hipGraph replay: a batch identical to a captured one (same operands,
+  // outputs, sizes, spectra, flags, status words) relaunches the captured
+  // kernel sequence without planning again.  Captured graphs are dropped
+  // whenever the engine's buffers or the tuning change.  The legacy null
+  // stream cannot be captured, so graphs need a created stream.
+  const bool graph = (flags & DMUL_FLAG_GRAPH) && ctx->stream != nullptr && !ctx->prof;
+  uint64_t sig = 1469598103934665603ULL;
+  if (graph) {
+    auto mix = [&sig](uint64_t v) { sig = (sig ^ v) * 1099511628211ULL; };
+    mix(count);
+    mix(flags);
+    mix((uint64_t)status_dev);
+    for (size_t i = 0; i < count; ++i) {
+      const dmul_spectrum* si = spec_a(i);
+      const dmul_spectrum* ti = spec_b(i);
+      mix((uint64_t)a[i]); mix(na[i]); mix((uint64_t)b[i]); mix(nb[i]); mix((uint64_t)out[i]);
+      mix(si ? (uint64_t)si->dev : 0); mix(ti ? (uint64_t)ti->dev : 0);
+    }
+    auto it = graphs_.find(sig);
+    if (it != graphs_.end()) {
+      for (size_t i = 0; i < count; ++i) {     // empty operands never enter a graph
+        if (na[i] == 0 || nb[i] == 0) {
+          const hipError_t e = launch_zero(out[i], na[i] + nb[i], ctx->stream);
+          if (e != hipSuccess) return from_hip(e);
+        }
+      }
+      if (hipEventRecord(copied_, ctx->stream) != hipSuccess) return DMUL_EDEVICE;
+      return from_hip(hipGraphLaunch(it->second.exec, ctx->stream));
+    }
+  }
   // plan, and group the products by transform length (and whether cached
   // spectra stand in for operands: those never take the one-workgroup kernel)
   std::vector<PlanDev> plans(count);
   std::map<std::pair<uint64_t, int>, std::vector<uint32_t>> classes;
-  auto spec_a = [&](size_t i) { return sa ? sa[i] : nullptr; };
-  auto spec_b = [&](size_t i) { return sb ? sb[i] : nullptr; };
   size_t ws_words = 0, sync_words = 0, nvalid = 0;
   for (size_t i = 0; i < count; ++i) {
     if (na[i] == 0 || nb[i] == 0) {
@@ -148,26 +178,6 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
     TwiddleSet tw;
     rc = get_twiddles(ctx, c.p0, &tw);
     if (rc) return rc;
-  }
-  // hipGraph replay: a batch identical to a captured one (same operands,
-  // outputs, sizes, flags) relaunches the captured kernel sequence.  The
-  // legacy null stream cannot be captured, so graphs need a created stream.
-  const bool graph = (flags & DMUL_FLAG_GRAPH) && ctx->stream != nullptr && !ctx->prof;
-  uint64_t sig = 1469598103934665603ULL;
-  auto mix = [&sig](uint64_t v) { sig = (sig ^ v) * 1099511628211ULL; };
-  if (graph) {
-    mix(nvalid);
-    mix(flags);
-    for (size_t i = 0; i < nvalid; ++i) {
-      const ProdDesc& d = h_desc_[i];
-      mix((uint64_t)d.a); mix((uint64_t)d.b); mix((uint64_t)d.out); mix(d.pl.na); mix(d.pl.nb);
-      mix((uint64_t)d.status); mix((uint64_t)d.ws); mix((uint64_t)d.xs); mix((uint64_t)d.ys);
-    }
-    auto it = graphs_.find(sig);
-    if (it != graphs_.end()) {
-      if (hipEventRecord(copied_, ctx->stream) != hipSuccess) return DMUL_EDEVICE;
-      return from_hip(hipGraphLaunch(it->second.exec, ctx->stream));
-    }
   }
   ProdDesc* descs = d_desc_;
   if (graph) {
