@@ -118,6 +118,21 @@ bool check_div_table(const DivTable& t) {
 
 namespace dmi {
 
+hipError_t allow_lds(const void* kernel, size_t lds_bytes) {
+  if (lds_bytes <= 64 * 1024) return hipSuccess;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, size_t> done;   // (kernel, device) -> bytes set
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = done.find({kernel, dev});
+  if (it != done.end() && it->second >= lds_bytes) return hipSuccess;
+  e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e == hipSuccess) done[{kernel, dev}] = lds_bytes;
+  return e;
+}
+
 int from_hip(hipError_t e) { return e == hipSuccess ? DMUL_OK : (e == hipErrorOutOfMemory ? DMUL_ENOMEM : DMUL_EDEVICE); }
 
 int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl) {

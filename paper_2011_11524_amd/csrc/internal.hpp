@@ -141,6 +141,9 @@ hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, cons
 bool small_fits(const PlanDev& pl, size_t count);
 hipError_t launch_small(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                         const DivTable* dt, const DivTable* dt_host, hipStream_t stream, Marks* marks);
+// Raises a kernel's dynamic-LDS limit to lds_bytes when above the default
+// 64 KB (once per kernel and size: the attribute call is host work).
+hipError_t allow_lds(const void* kernel, size_t lds_bytes);
 size_t recover_blocks(const PlanDev& pl);
 size_t recover_scratch_words(const PlanDev& pl);
 hipError_t launch_zero(uint64_t* out, size_t n, hipStream_t stream);

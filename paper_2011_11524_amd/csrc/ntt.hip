@@ -368,10 +368,7 @@ constexpr int rows_per_wg(int logl) {
 
 template <typename K>
 static hipError_t prepare(K kernel, size_t lds_bytes) {
-  if (lds_bytes > 64 * 1024)
-    return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds_bytes);
-  return hipSuccess;
+  return allow_lds((const void*)kernel, lds_bytes);
 }
 
 template <int LOGR, bool R3>

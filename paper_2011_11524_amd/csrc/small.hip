@@ -181,11 +181,8 @@ static hipError_t small_launch(const Work& w, const Consts& cs, const TwiddleSet
                                const RecTable& rt, hipStream_t st) {
   const size_t lds = small_lds_words(LOGM, R3 ? 3 : 1) * sizeof(uint64_t);
   auto kern = k_small<LOGM, R3>;
-  if (lds > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)lds);
-    if (e != hipSuccess) return e;
-  }
+  const hipError_t e = allow_lds((const void*)kern, lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(1, 1, w.count), dim3(kSmallThreads), lds, st, w, cs, tw, dt, rt);
   return hipGetLastError();
 }
