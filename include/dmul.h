@@ -193,17 +193,21 @@ const char* dmul_phase_name(int phase);
  * dmul_spectrum_create: a: device pointer to na limbs (only read by the
  *   work enqueued here: it may be freed once that work is done).  Enqueues
  *   the transforms on ctx's stream; a limb >= 10^19 is reported by the next
- *   dmul_sync (DMUL_EDIGIT).  The spectrum owns dmul_spectrum_bytes(na, nb,
- *   flags) = 16 N bytes of device memory, outside the context's budget,
- *   until dmul_spectrum_destroy.  Returns DMUL_OK and *spec, or DMUL_EINVAL
- *   (NULL, empty operand, bad flags), DMUL_ERANGE, DMUL_ENOMEM, DMUL_EDEVICE.
- * dmul_spectrum_destroy: frees it; the caller makes sure no queued work
- *   still reads it (dmul_sync on every context that used it).
+ *   dmul_sync (DMUL_EDIGIT).  The transforms take dmul_spectrum_bytes(na,
+ *   nb, flags) = 16 N bytes of device memory: the caller's (mem, at least
+ *   that many bytes, 8-byte aligned, owned by the caller and not touched
+ *   until the spectrum is destroyed), or, with mem NULL, the library's own
+ *   allocation, outside the context's budget.  Returns DMUL_OK and *spec,
+ *   or DMUL_EINVAL (NULL, empty operand, bad flags, mem too small or
+ *   misaligned), DMUL_ERANGE, DMUL_ENOMEM, DMUL_EDEVICE.
+ * dmul_spectrum_destroy: releases it (and frees the library's allocation);
+ *   the caller makes sure no queued work still reads it (dmul_sync on every
+ *   context that used it).
  * Spectra belong to the device of the context that made them; use them on
  * another stream only after dmul_sync on the creating context. */
 typedef struct dmul_spectrum dmul_spectrum;
 int dmul_spectrum_create(dmul_ctx* ctx, const uint64_t* a, size_t na, size_t nb, unsigned flags,
-                         dmul_spectrum** spec);
+                         void* mem, size_t mem_bytes, dmul_spectrum** spec);
 int dmul_spectrum_destroy(dmul_spectrum* spec);
 size_t dmul_spectrum_bytes(size_t na, size_t nb, unsigned flags);
 
