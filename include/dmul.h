@@ -69,7 +69,8 @@ extern "C" {
  * submitted again on the same context.  Needs a context stream set by
  * dmul_ctx_set_stream (the legacy null stream cannot be captured); without
  * one the flag is ignored.  Captured batches are dropped when the context's
- * batch buffers grow (at most 8 are kept). */
+ * batch buffers grow or its tuning changes (at most 8 are kept).  A batch in
+ * which some product fails planning is run without capture. */
 #define DMUL_FLAG_GRAPH 0x100u
 /* Use a power-of-two transform length even where 3 * 2^e is shorter (for
  * tests and comparisons; the product is the same). */
@@ -109,7 +110,10 @@ int dmul_ctx_create(dmul_ctx** ctx, int device, size_t hbm_budget_bytes);
 /* Waits for the context's work, then frees everything it owns. */
 int dmul_ctx_destroy(dmul_ctx* ctx);
 /* The HIP stream (hipStream_t passed as void*) the context enqueues on;
- * NULL selects the null stream.  The stream stays owned by the caller. */
+ * NULL selects the null stream.  The stream stays owned by the caller.
+ * Waits for the work already queued on the previous stream (it shares the
+ * context's buffers); a pending device error is still reported by the next
+ * dmul_sync. */
 int dmul_ctx_set_stream(dmul_ctx* ctx, void* hip_stream);
 
 /* Asynchronous product: enqueues the whole product on the context's stream
@@ -203,8 +207,9 @@ const char* dmul_phase_name(int phase);
  * dmul_spectrum_destroy: releases it (and frees the library's allocation);
  *   the caller makes sure no queued work still reads it (dmul_sync on every
  *   context that used it).
- * Spectra belong to the device of the context that made them; use them on
- * another stream only after dmul_sync on the creating context. */
+ * Spectra belong to the device of the context that made them (a context of
+ * another device refuses them with DMUL_EINVAL); use them on another stream
+ * only after dmul_sync on the creating context. */
 typedef struct dmul_spectrum dmul_spectrum;
 int dmul_spectrum_create(dmul_ctx* ctx, const uint64_t* a, size_t na, size_t nb, unsigned flags,
                          void* mem, size_t mem_bytes, dmul_spectrum** spec);

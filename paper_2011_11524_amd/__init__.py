@@ -402,6 +402,11 @@ def mul(a, b, force_k: int = 0, pow2: bool = False):
         ctx = _default_context(a.device.index or 0)
         return ctx.mul(a, b, force_k, out, pow2)
     with torch.cuda.device(a.device):
+        # dmul runs on the null stream: operands made on another current
+        # stream must be complete first
+        cur = torch.cuda.current_stream()
+        if cur.cuda_stream != 0:
+            cur.synchronize()
         rc = lib().dmul(ctypes.c_void_p(a.data_ptr() if a.numel() else 0), a.numel(),
                         ctypes.c_void_p(b.data_ptr() if b.numel() else 0), b.numel(),
                         ctypes.c_void_p(out.data_ptr() if out.numel() else 0))

@@ -355,9 +355,10 @@ int check_args(const uint64_t* a, size_t na, const uint64_t* b, size_t nb, const
 // The plan of a product whose operands may come as cached spectra: the plan
 // of (na, nb) must have the k and transform length every given spectrum was
 // made for (DMUL_EINVAL otherwise).
-int spectrum_plan(const dmul_spectrum* sa, size_t na, const dmul_spectrum* sb, size_t nb,
+int spectrum_plan(int device, const dmul_spectrum* sa, size_t na, const dmul_spectrum* sb, size_t nb,
                   unsigned flags, PlanDev* pl) {
   if ((sa && sa->na != na) || (sb && sb->na != nb)) return DMUL_EINVAL;
+  if ((sa && sa->device != device) || (sb && sb->device != device)) return DMUL_EINVAL;
   const int rc = make_plan(na, nb, flags, pl);
   if (rc) return rc;
   for (const dmul_spectrum* s : {sa, sb}) {
@@ -372,7 +373,7 @@ int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t*
                     const dmul_spectrum* sa, const dmul_spectrum* sb) {
   if (na == 0 || nb == 0) return from_hip(launch_zero(out, na + nb, ctx->stream));
   PlanDev pl;
-  int rc = spectrum_plan(sa, na, sb, nb, flags, &pl);
+  int rc = spectrum_plan(ctx->device, sa, na, sb, nb, flags, &pl);
   if (rc) return rc;
   TwiddleSet tw;
   rc = get_twiddles(ctx, pl, &tw);
@@ -608,6 +609,10 @@ int dmul_ctx_destroy(dmul_ctx* c) {
 int dmul_ctx_set_stream(dmul_ctx* c, void* stream) {
   if (!c) return DMUL_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
+  if ((hipStream_t)stream == c->stream) return DMUL_OK;
+  // work queued on the old stream uses the context's buffers and status
+  // words: it completes before anything is enqueued on the new one
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return DMUL_EDEVICE;
   c->stream = (hipStream_t)stream;
   return DMUL_OK;
 }
@@ -703,7 +708,7 @@ int dmul_ctx_tune(dmul_ctx* c, uint64_t transform_len, int row_iters) {
   if (!c || !size_class(transform_len, &r3, &e) || row_iters < 0 || row_iters > 64) return DMUL_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
   c->tune.row_iters[r3][e] = row_iters;
-  if (c->batch) c->batch->forget_graphs();
+  if (c->batch) c->batch->forget_graphs(c->stream);
   return DMUL_OK;
 }
 

@@ -84,21 +84,32 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
   // kernel sequence without planning again.  Captured graphs are dropped
   // whenever the engine's buffers or the tuning change.  The legacy null
   // stream cannot be captured, so graphs need a created stream.
-  const bool graph = (flags & DMUL_FLAG_GRAPH) && ctx->stream != nullptr && !ctx->prof;
+  bool graph = (flags & DMUL_FLAG_GRAPH) && ctx->stream != nullptr && !ctx->prof;
   uint64_t sig = 1469598103934665603ULL;
+  std::vector<uint64_t> key;
   if (graph) {
-    auto mix = [&sig](uint64_t v) { sig = (sig ^ v) * 1099511628211ULL; };
-    mix(count);
-    mix(flags);
-    mix((uint64_t)status_dev);
+    key.reserve(3 + 13 * count);
+    key.push_back(count);
+    key.push_back(flags);
+    key.push_back((uint64_t)status_dev);
+    auto spec = [&key](const dmul_spectrum* s) {
+      key.push_back(s ? (uint64_t)s->dev : 0);
+      key.push_back(s ? s->na : 0);
+      key.push_back(s ? s->pl.N : 0);
+      key.push_back(s ? (uint64_t)s->pl.k : 0);
+    };
     for (size_t i = 0; i < count; ++i) {
-      const dmul_spectrum* si = spec_a(i);
-      const dmul_spectrum* ti = spec_b(i);
-      mix((uint64_t)a[i]); mix(na[i]); mix((uint64_t)b[i]); mix(nb[i]); mix((uint64_t)out[i]);
-      mix(si ? (uint64_t)si->dev : 0); mix(ti ? (uint64_t)ti->dev : 0);
+      key.push_back((uint64_t)a[i]);
+      key.push_back(na[i]);
+      key.push_back((uint64_t)b[i]);
+      key.push_back(nb[i]);
+      key.push_back((uint64_t)out[i]);
+      spec(spec_a(i));
+      spec(spec_b(i));
     }
+    for (uint64_t v : key) sig = (sig ^ v) * 1099511628211ULL;
     auto it = graphs_.find(sig);
-    if (it != graphs_.end()) {
+    if (it != graphs_.end() && it->second.key == key) {
       for (size_t i = 0; i < count; ++i) {     // empty operands never enter a graph
         if (na[i] == 0 || nb[i] == 0) {
           const hipError_t e = launch_zero(out[i], na[i] + nb[i], ctx->stream);
@@ -120,10 +131,11 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       if (e != hipSuccess) return from_hip(e);
       continue;
     }
-    const int rc = spectrum_plan(spec_a(i), na[i], spec_b(i), nb[i],
+    const int rc = spectrum_plan(ctx->device, spec_a(i), na[i], spec_b(i), nb[i],
                                  flags & (DMUL_FLAG_K_MASK | DMUL_FLAG_POW2), &plans[i]);
     if (rc) {
       status[i] = rc;
+      graph = false;     // a replay would not report this product's error
       continue;
     }
     classes[{plans[i].N, (spec_a(i) || spec_b(i)) ? 1 : 0}].push_back((uint32_t)i);
@@ -181,7 +193,10 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
   }
   ProdDesc* descs = d_desc_;
   if (graph) {
-    if (graphs_.size() >= 8) drop_graphs();
+    if (graphs_.size() >= 8) {
+      if (hipStreamSynchronize(ctx->stream) != hipSuccess) return DMUL_EDEVICE;
+      drop_graphs();
+    }
     hipError_t e = hipMalloc(&descs, nvalid * sizeof(ProdDesc));
     if (e != hipSuccess) return from_hip(e);
   }
@@ -226,6 +241,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
     if (e == hipSuccess) e = ec;
     Graph entry;
     entry.descs = descs;
+    entry.key = std::move(key);
     if (e == hipSuccess && !rc) e = hipGraphInstantiate(&entry.exec, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     if (e == hipSuccess && !rc) e = hipGraphLaunch(entry.exec, ctx->stream);
@@ -235,7 +251,14 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       (void)hipFree(descs);
       return rc ? rc : from_hip(e);
     }
-    graphs_[sig] = entry;
+    auto old = graphs_.find(sig);
+    if (old != graphs_.end()) {             // same hash, other batch: the newer one stays
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipGraphExecDestroy(old->second.exec);
+      (void)hipFree(old->second.descs);
+      graphs_.erase(old);
+    }
+    graphs_.emplace(sig, std::move(entry));
   }
   if (rc) return rc;
   return from_hip(e);

@@ -21,8 +21,12 @@ class BatchEngine {
   ~BatchEngine();
   // Enqueues `count` products on the context's stream; status_dev[i] is the
   // device word product i reports to.  Host-side errors go to status[i].
-  // Captured graphs bake in launch parameters: drop them when those change.
-  void forget_graphs() { drop_graphs(); }
+  // Captured graphs bake in launch parameters: drop them when those change
+  // (after the work queued on st, which may still run them, is done).
+  void forget_graphs(hipStream_t st) {
+    (void)hipStreamSynchronize(st);
+    drop_graphs();
+  }
   int run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, const size_t* na,
           const dmul_spectrum* const* sa, const uint64_t* const* b, const size_t* nb,
           const dmul_spectrum* const* sb, uint64_t* const* out, int32_t* status,
@@ -32,13 +36,14 @@ class BatchEngine {
   int reserve(dmul_ctx* ctx, size_t ws_words, size_t sync_words, size_t ndesc);
   void drop_graphs();
 
-  // Captured batches, by a hash of everything the launches depend on.
+  // Captured batches, by a hash of everything the launches depend on; a
+  // replay also needs the whole key to match.
   struct Graph {
     hipGraphExec_t exec = nullptr;
     ProdDesc* descs = nullptr;      // the batch's own descriptor copy
+    std::vector<uint64_t> key;
   };
   std::map<uint64_t, Graph> graphs_;
-  uint64_t graph_seq_ = 0;
 
   uint64_t* ws_ = nullptr;          // per-product workspaces, back to back
   size_t ws_words_ = 0;

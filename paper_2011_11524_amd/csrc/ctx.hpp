@@ -126,6 +126,8 @@ int from_hip(hipError_t e);
 int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
                     uint64_t* out, unsigned flags, int* status, uint64_t* residues,
                     const dmul_spectrum* sa = nullptr, const dmul_spectrum* sb = nullptr);
-int spectrum_plan(const dmul_spectrum* sa, size_t na, const dmul_spectrum* sb, size_t nb,
+// Plan of a product on `device` whose operands may be spectra: DMUL_EINVAL
+// when a spectrum belongs to another device, length or plan.
+int spectrum_plan(int device, const dmul_spectrum* sa, size_t na, const dmul_spectrum* sb, size_t nb,
                   unsigned flags, PlanDev* pl);
 }  // namespace dmi

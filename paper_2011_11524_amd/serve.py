@@ -114,6 +114,7 @@ class Server:
         self._spectra = OrderedDict()   # (offset, limbs, k, N) -> [Spectrum, bytes, event, stream]
         self._spec_bytes = 0
         self._seen = {}                 # operand key -> times used
+        self._seen_cap = 1 << 20
         self._stats = None
         lib()
 
@@ -140,6 +141,8 @@ class Server:
             self._stats.spectrum_hits += 1
             return ent[0]
         seen = self._seen.get(key, 0)
+        if len(self._seen) >= self._seen_cap:   # forget old sightings in a long run
+            self._seen.clear()
         self._seen[key] = seen + 1
         nbytes = spectrum_bytes(n, partner)
         if seen == 0 or nbytes > self.spec_cap:

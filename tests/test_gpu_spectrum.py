@@ -173,3 +173,34 @@ def test_spectrum_in_caller_memory(dm, ctx):
     with pytest.raises(dm.DmulError) as e:
         ctx.spectrum(da, nb, mem=small)
     assert e.value.code == dm.DMUL_EINVAL
+
+
+def test_graph_batch_with_a_failing_product(dm):
+    """A graph batch in which one product cannot be planned (its spectrum was
+    made for another partner length): every submission reports that
+    product's DMUL_EINVAL and computes the others, so no replay hides it."""
+    import torch
+    _note("graph batch with a failing product")
+    s = torch.cuda.Stream()
+    ctx = dm.Context(0, stream=s)
+    try:
+        rng = np.random.default_rng(606)
+        a, b = _limbs(rng, 3000), _limbs(rng, 2500)
+        c, e = _limbs(rng, 40000), _limbs(rng, 100)
+        da, db, dc, de = (dm.to_device(x) for x in (a, b, c, e))
+        sa = ctx.spectrum(da, 2500)                      # for partners of 2500 limbs
+        pairs = [(da, db), (sa, dc), (dc, de), (sa, db)]  # the second needs another N
+        want = [oracle.mul_ntt(a, b), None, oracle.mul_ntt(c, e), oracle.mul_ntt(a, b)]
+        outs = [torch.zeros(n, dtype=torch.uint64, device="cuda") for n in (5500, 43000, 40100, 5500)]
+        for rep in range(3):
+            for o in outs:
+                o.zero_()
+            torch.cuda.synchronize()
+            _, st = ctx.batch(pairs, graph=True, outs=outs)
+            assert st == [0, dm.DMUL_EINVAL, 0, 0], (rep, st)
+            for o, w in zip(outs, want):
+                if w is not None:
+                    np.testing.assert_array_equal(dm.to_host(o), w)
+        sa.close()
+    finally:
+        ctx.close()
