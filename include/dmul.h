@@ -105,7 +105,9 @@ typedef struct dmul_plan_info {
 int dmul(const uint64_t* a, size_t na, const uint64_t* b, size_t nb, uint64_t* out);
 
 /* Context on `device` with a workspace budget in bytes (0 = no limit).
- * Returns DMUL_OK and *ctx, or DMUL_EDEVICE / DMUL_ENOMEM. */
+ * Returns DMUL_OK and *ctx, or DMUL_EDEVICE / DMUL_ENOMEM.  Every call on
+ * a context (or a spectrum) works on the context's device and leaves the
+ * calling thread's current HIP device as it found it. */
 int dmul_ctx_create(dmul_ctx** ctx, int device, size_t hbm_budget_bytes);
 /* Waits for the context's work, then frees everything it owns. */
 int dmul_ctx_destroy(dmul_ctx* ctx);

@@ -512,8 +512,9 @@ int dmul_ctx_create(dmul_ctx** out, int device, size_t budget) {
   if (!check_field()) return DMUL_EDEVICE;
   const DivTable dt = make_div_table();
   if (!check_div_table(dt)) return DMUL_EDEVICE;
-  hipError_t e = hipSetDevice(device);
-  if (e != hipSuccess) return from_hip(e);
+  DeviceGuard dg(device);
+  if (!dg.ok()) return DMUL_EDEVICE;
+  hipError_t e = hipSuccess;
   dmul_ctx* c = new (std::nothrow) dmul_ctx;
   if (!c) return DMUL_ENOMEM;
   c->device = device;
@@ -591,7 +592,7 @@ int dmul_ctx_create(dmul_ctx** out, int device, size_t budget) {
 
 int dmul_ctx_destroy(dmul_ctx* c) {
   if (!c) return DMUL_EINVAL;
-  (void)hipSetDevice(c->device);
+  DeviceGuard dg(c->device);
   (void)hipStreamSynchronize(c->stream);
   delete c->batch;
   delete c->prof;
@@ -608,6 +609,8 @@ int dmul_ctx_destroy(dmul_ctx* c) {
 
 int dmul_ctx_set_stream(dmul_ctx* c, void* stream) {
   if (!c) return DMUL_EINVAL;
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return DMUL_EDEVICE;
   std::lock_guard<std::mutex> lk(c->mu);
   if ((hipStream_t)stream == c->stream) return DMUL_OK;
   // work queued on the old stream uses the context's buffers and status
@@ -622,6 +625,8 @@ int dmul_ex(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_t* b, size_t
   if (!c) return DMUL_EINVAL;
   int rc = check_args(a, na, b, nb, out);
   if (rc) return rc;
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return DMUL_EDEVICE;
   std::lock_guard<std::mutex> lk(c->mu);
   rc = enqueue_product(c, a, na, b, nb, out, flags, c->d_status, nullptr);
   if (rc == DMUL_EDEVICE && c->pending == DMUL_OK) c->pending = rc;
@@ -630,6 +635,8 @@ int dmul_ex(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_t* b, size_t
 
 int dmul_sync(dmul_ctx* c) {
   if (!c) return DMUL_EINVAL;
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return DMUL_EDEVICE;
   std::lock_guard<std::mutex> lk(c->mu);
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e == hipSuccess && c->prof) c->prof->collect();
@@ -667,7 +674,8 @@ int dmul(const uint64_t* a, size_t na, const uint64_t* b, size_t nb, uint64_t* o
 int dmul_host(int device, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
               uint64_t* out, unsigned flags) {
   if ((na && !a) || (nb && !b) || (na + nb && !out)) return DMUL_EINVAL;
-  if (hipSetDevice(device) != hipSuccess) return DMUL_EDEVICE;
+  DeviceGuard dg(device);
+  if (!dg.ok()) return DMUL_EDEVICE;
   int rc = DMUL_OK;
   dmul_ctx* c = default_ctx(device, &rc);
   if (!c) return rc;
@@ -694,6 +702,8 @@ int dmul_host(int device, const uint64_t* a, size_t na, const uint64_t* b, size_
 int dmul_debug_residues(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
                         uint64_t* res, unsigned flags) {
   if (!c || !res || !na || !nb || !a || !b) return DMUL_EINVAL;
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return DMUL_EDEVICE;
   int rc;
   {
     std::lock_guard<std::mutex> lk(c->mu);
@@ -706,6 +716,7 @@ int dmul_debug_residues(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_
 int dmul_ctx_tune(dmul_ctx* c, uint64_t transform_len, int row_iters) {
   int r3 = 0, e = 0;
   if (!c || !size_class(transform_len, &r3, &e) || row_iters < 0 || row_iters > 64) return DMUL_EINVAL;
+  DeviceGuard dg(c->device);
   std::lock_guard<std::mutex> lk(c->mu);
   c->tune.row_iters[r3][e] = row_iters;
   if (c->batch) c->batch->forget_graphs(c->stream);
@@ -714,6 +725,7 @@ int dmul_ctx_tune(dmul_ctx* c, uint64_t transform_len, int row_iters) {
 
 int dmul_ctx_profile(dmul_ctx* c, int enable) {
   if (!c) return DMUL_EINVAL;
+  DeviceGuard dg(c->device);
   std::lock_guard<std::mutex> lk(c->mu);
   (void)hipStreamSynchronize(c->stream);
   delete c->prof;
@@ -768,6 +780,8 @@ int dmul_batch_ex(dmul_ctx* c, size_t count, const uint64_t* const* a, const siz
     if (rc) return rc;
     if ((si || ti) && !out[i]) return DMUL_EINVAL;
   }
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return DMUL_EDEVICE;
   std::lock_guard<std::mutex> lk(c->mu);
   int rc = ensure_status(c, 1 + count);
   if (rc) return rc;
@@ -805,6 +819,8 @@ int dmul_spectrum_create(dmul_ctx* c, const uint64_t* a, size_t na, size_t nb, u
   if (rc) return rc;
   const size_t bytes = 2 * (size_t)pl.N * sizeof(uint64_t);
   if (mem && (mem_bytes < bytes || ((uintptr_t)mem & 7))) return DMUL_EINVAL;
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return DMUL_EDEVICE;
   std::lock_guard<std::mutex> lk(c->mu);
   TwiddleSet tw;
   rc = get_twiddles(c, pl, &tw);
@@ -851,6 +867,7 @@ int dmul_spectrum_create(dmul_ctx* c, const uint64_t* a, size_t na, size_t nb, u
 
 int dmul_spectrum_destroy(dmul_spectrum* s) {
   if (!s) return DMUL_EINVAL;
+  DeviceGuard dg(s->device);
   if (s->dev && s->owned) (void)hipFree(s->dev);
   delete s;
   return DMUL_OK;
@@ -865,6 +882,8 @@ int dmul_ex_spectrum(dmul_ctx* c, const dmul_spectrum* sa, const uint64_t* b, si
     const int rc = check_args(nullptr, 0, b, nb, out);
     if (rc) return rc;
   }
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return DMUL_EDEVICE;
   std::lock_guard<std::mutex> lk(c->mu);
   const int rc = enqueue_product(c, nullptr, sa->na, b, nb, out, flags, c->d_status, nullptr, sa, sb);
   if (rc == DMUL_EDEVICE && c->pending == DMUL_OK) c->pending = rc;

@@ -115,6 +115,36 @@ struct dmul_spectrum {
 };
 
 namespace dmi {
+// Makes `device` current for the scope of an entry point and gives the
+// caller back its own current device afterwards: a context's work goes to
+// the context's device whatever device the calling thread has selected.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int device) {
+    if (hipGetDevice(&prev_) != hipSuccess) {
+      err_ = hipErrorInvalidDevice;
+      return;
+    }
+    if (prev_ != device) {
+      err_ = hipSetDevice(device);
+      changed_ = err_ == hipSuccess;
+      // the failed call's error must not surface at the next launch check
+      if (!changed_) (void)hipGetLastError();
+    }
+  }
+  ~DeviceGuard() {
+    if (changed_) (void)hipSetDevice(prev_);
+  }
+  DeviceGuard(const DeviceGuard&) = delete;
+  DeviceGuard& operator=(const DeviceGuard&) = delete;
+  bool ok() const { return err_ == hipSuccess; }
+
+ private:
+  int prev_ = 0;
+  bool changed_ = false;
+  hipError_t err_ = hipSuccess;
+};
+
 int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl);
 size_t workspace_words(const PlanDev& pl);
 int get_twiddles(dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw);

@@ -369,6 +369,28 @@ def test_default_context_and_host_entry(dm):
     np.testing.assert_array_equal(dm.mul_host(a, b, force_k=15), want)
 
 
+def test_device_selection(dm):
+    """Context calls leave the thread's current device alone; a context on a
+    device that does not exist is refused (DMUL_EDEVICE) and nothing else
+    is disturbed."""
+    import torch
+    _note("device selection")
+    before = torch.cuda.current_device()
+    with pytest.raises(dm.DmulError) as e:
+        dm.Context(torch.cuda.device_count() + 7)
+    assert e.value.code == dm.DMUL_EDEVICE
+    assert torch.cuda.current_device() == before
+    rng = random.Random(5)
+    a, b = _rand_limbs(rng, 2000), _rand_limbs(rng, 1500)
+    c = dm.Context(before)
+    try:
+        got = dm.to_host(c.mul(dm.to_device(a), dm.to_device(b)))
+    finally:
+        c.close()
+    assert torch.cuda.current_device() == before
+    np.testing.assert_array_equal(got, oracle.mul_ntt(a, b))
+
+
 def test_batch_matches_single_and_oracle(dm, ctx):
     _note("batch mixed sizes")
     rng = random.Random(4242)
