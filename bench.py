@@ -68,6 +68,9 @@ def phase_work(N: int, logR: int, logC: int, factor: int, arrays_fwd: int, NP: i
     w["fwd_rows"] = (arrays_fwd * (fwd_stage(logC) + r3), arrays_fwd * 16 * N)
     w["inv_rows"] = (2 * (N * OPS_MODMUL + inv_stage(logC) + r3), 2 * 24 * N)
     w["inv_cols"] = (2 * (2 * N * OPS_MODMUL + inv_stage(logR)), 2 * 16 * N)
+    # fwd_rows, pointwise and inv_rows in one pass: reads the A column-pass
+    # arrays, writes the two product arrays
+    w["rows"] = (w["fwd_rows"][0] + w["inv_rows"][0], arrays_fwd * 8 * N + 2 * 8 * N)
     w["rec_crt"] = (NP * OPS_CRT, 24 * NP)
     w["rec_apply"] = (NP * OPS_CARRY, 8 * NP + 8 * (na + nb))
     return w
@@ -382,7 +385,7 @@ def main() -> int:
                 "unit": "TOP/s", "frac": round(d["valu_tops"] / VALU_PEAK_TOPS, 4),
                 "ops_per_launch": ops_dom, "bytes_per_launch": bytes_dom,
                 "traffic": traffic_for(dominant, "bytes")}
-    ntt = [k for k in ("fwd_cols", "fwd_rows", "inv_rows", "inv_cols") if k in phases]
+    ntt = [k for k in ("fwd_cols", "fwd_rows", "rows", "inv_rows", "inv_cols") if k in phases]
     ntt_s = sum(phases[k]["avg_us"] for k in ntt) / 1e6
     ntt_bytes = sum(work[k][1] for k in ntt)
     hbm = {"ntt_phases_gbs": round(ntt_bytes / ntt_s / 1e9, 1), "peak": HBM_PEAK_GBS,

@@ -402,8 +402,13 @@ int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t*
   if (ctx->prof) ctx->prof->begin(ctx->stream);
   if (!residues && !sa && !sb && small_fits(pl, 1))
     return from_hip(launch_small(w, sh, ctx->cs, tw, ctx->d_div, &ctx->h_div, ctx->stream, marks));
-  hipError_t e = launch_forward(w, sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
-  if (e == hipSuccess) e = launch_inverse(w, sh, ctx->cs, tw, ctx->stream, marks);
+  hipError_t e;
+  if (sa || sb) {
+    e = launch_forward(w, sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
+    if (e == hipSuccess) e = launch_inverse(w, sh, ctx->cs, tw, ctx->stream, marks);
+  } else {
+    e = launch_fused(w, sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
+  }
   if (e != hipSuccess) return from_hip(e);
   if (residues) {
     e = hipMemcpyAsync(residues, ctx->ws, 2 * pl.N * sizeof(uint64_t), hipMemcpyDeviceToDevice, ctx->stream);
@@ -761,7 +766,7 @@ int dmul_ctx_profile_events(dmul_ctx* c, int32_t* phases, double* end_ms, int n)
 
 const char* dmul_phase_name(int phase) {
   static const char* names[kNumPhases] = {"fwd_cols", "fwd_rows", "inv_rows", "inv_cols",
-                                          "rec_crt", "rec_apply", "whole"};
+                                          "rec_crt", "rec_apply", "whole", "rows"};
   return (phase >= 0 && phase < kNumPhases) ? names[phase] : "unknown";
 }
 

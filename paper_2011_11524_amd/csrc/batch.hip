@@ -229,8 +229,12 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
         e = launch_small(w, c.sh, ctx->cs, tw, ctx->d_div, &ctx->h_div, ctx->stream, marks);
         continue;
       }
-      e = launch_forward(w, c.sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
-      if (e == hipSuccess) e = launch_inverse(w, c.sh, ctx->cs, tw, ctx->stream, marks);
+      if (c.spectra) {
+        e = launch_forward(w, c.sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
+        if (e == hipSuccess) e = launch_inverse(w, c.sh, ctx->cs, tw, ctx->stream, marks);
+      } else {
+        e = launch_fused(w, c.sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
+      }
       if (e == hipSuccess) e = launch_recover(w, c.sh, ctx->cs, ctx->d_div, &ctx->h_div, ctx->stream, marks);
     }
     if (e != hipSuccess) break;

@@ -82,7 +82,7 @@ constexpr size_t kR3TableWords = 2 * (((size_t)1 << (kMaxLogC3 + 1)) - 1);
 
 // Optional per-kernel timing: when set, a launch wrapper records an event on
 // the stream after each kernel it launches (phase ids below).
-enum Phase { kFwdCols = 0, kFwdRows, kInvRows, kInvCols, kRecCrt, kRecApply, kWhole, kNumPhases };
+enum Phase { kFwdCols = 0, kFwdRows, kInvRows, kInvCols, kRecCrt, kRecApply, kWhole, kRows, kNumPhases };
 struct Marks {
   virtual void mark(int phase, hipStream_t st) = 0;
   virtual ~Marks() = default;
@@ -132,6 +132,11 @@ hipError_t launch_forward(const Work& w, const Shape& sh, const Consts& cs, cons
                           const DivTable* dt, hipStream_t stream, Marks* marks);
 hipError_t launch_inverse(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                           hipStream_t stream, Marks* marks);
+// The three transform passes of products without cached spectra: forward
+// columns, then the rows in both directions with the pointwise product, then
+// inverse columns (the same residues as launch_forward + launch_inverse).
+hipError_t launch_fused(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                        const DivTable* dt, hipStream_t stream, Marks* marks);
 hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, const DivTable* dt,
                           const DivTable* dt_host, hipStream_t stream, Marks* marks);
 // Whole products in one workgroup (small.hip): for N <= kSmallMaxN when a

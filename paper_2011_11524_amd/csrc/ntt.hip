@@ -250,6 +250,88 @@ k_rows(Work w, Consts cs, TwiddleSet tw) {
 }
 
 // ---------------------------------------------------------------------------
+// Pass B in both directions at once, for products whose operands are both
+// transformed here (no cached spectra): once the forward column pass is
+// done, each row's forward DIF, its pointwise REDC product and its inverse
+// DIT involve that row alone (Section 7.4), so one workgroup takes a row
+// through all three and the forward spectra never go back to HBM.  X's
+// spectrum waits in registers, as the points t + j*NT that the inverse
+// starts from, while Y's goes through the same LDS row; the product is
+// formed in LDS and the inverse rounds run on it.  Rows beyond R are
+// computed on zeros and not stored.  grid.y = prime, grid.z = product.
+// ---------------------------------------------------------------------------
+template <int LOGC, int LOGE, int RPW>
+__global__ void __launch_bounds__((RPW * Geometry<LOGC, LOGE>::NT), (LOGE == 3 ? 4 : 1))
+k_rows_fused(Work w, Consts cs, TwiddleSet tw) {
+  using G = Geometry<LOGC, LOGE>;
+  constexpr int C = G::L, E = G::E, NT = G::NT;
+  constexpr int NR = G::ROUNDS;
+  constexpr bool kWave = NT <= 64;               // each row within one wavefront
+  extern __shared__ uint64_t lds[];
+  const ProdDesc d = load_desc(w);
+  const int pi = blockIdx.y;
+  const Prime P = cs.P[pi];
+  uint64_t* X = d.ws + (size_t)pi * d.pl.N;
+  const uint64_t* Y = d.ws + (size_t)(2 + pi) * d.pl.N;
+  const bool square = d.square != 0;
+  const uint64_t R = (uint64_t)(d.pl.rad3 ? 3 : 1) << d.pl.logR;  // rows of C points
+  const uint32_t groups = (uint32_t)((R + RPW - 1) / RPW);
+  const int r = threadIdx.x / NT, t = threadIdx.x % NT;
+  uint64_t* row_lds = lds + r * G::STRIDE;
+  uint64_t* rf = lds + RPW * G::STRIDE;          // forward roots of the row length
+  uint64_t* ri = rf + C / 2;                     // inverse roots
+  for (int i = threadIdx.x; i < C / 2; i += blockDim.x) {
+    rf[i] = tw.len_fwd[pi][root_table_offset(LOGC) + i];
+    ri[i] = tw.len_inv[pi][root_table_offset(LOGC) + i];
+  }
+  __syncthreads();
+
+  using R0 = typename RoundBits<LOGC, LOGE, false, 0>::type;
+  using RL = typename RoundBits<LOGC, LOGE, true, NR - 1>::type;
+  uint64_t cur[E], xs[E];
+  for (uint32_t g = blockIdx.x; g < groups; g += gridDim.x) {
+    const uint64_t row = (uint64_t)g * RPW + r;
+    const bool in = row < R;
+    // forward DIF of X's row: round 0 on the loaded registers, the rest in LDS
+#pragma unroll
+    for (int j = 0; j < E; ++j) cur[j] = in ? X[row * C + t + j * NT] : 0;
+    R0::compute(cur, rf, P, t);
+    R0::store(row_lds, cur, t);
+    round_sync<kWave>();
+    RoundRange<LOGC, LOGE, false, 1, NR, kWave>::run(row_lds, rf, P, t);
+#pragma unroll
+    for (int j = 0; j < E; ++j) xs[j] = row_lds[lds_pos<LOGE>(t + j * NT)];
+    if (square) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) row_lds[lds_pos<LOGE>(t + j * NT)] = mont_mul(xs[j], xs[j], P);
+    } else {
+      round_sync<kWave>();                       // X's spectrum read before Y's overwrites the row
+#pragma unroll
+      for (int j = 0; j < E; ++j) cur[j] = in ? Y[row * C + t + j * NT] : 0;
+      R0::compute(cur, rf, P, t);
+      R0::store(row_lds, cur, t);
+      round_sync<kWave>();
+      RoundRange<LOGC, LOGE, false, 1, NR, kWave>::run(row_lds, rf, P, t);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int o = lds_pos<LOGE>(t + j * NT);
+        row_lds[o] = mont_mul(xs[j], row_lds[o], P);
+      }
+    }
+    round_sync<kWave>();
+    // inverse DIT: all rounds but the last in LDS, the last ends in registers
+    RoundRange<LOGC, LOGE, true, 0, NR - 1, kWave>::run(row_lds, ri, P, t);
+    RL::load(row_lds, cur, t);
+    RL::compute(cur, ri, P, t);
+    if (in) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) X[row * C + RL::index(t, j)] = cur[j];
+    }
+    round_sync<kWave>();   // the next group reuses the LDS rows
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Pass A, inverse: (for C = 3M first the factor w_C^(-s*q) and the inverse
 // length-3 DFT across the thirds of each row, completing the row
 // transform), inter-pass factor with scale, then column DIT; the result is
@@ -421,6 +503,31 @@ static hipError_t rows_l(const Work& w, const Shape& sh, const Consts& cs, const
   return hipGetLastError();
 }
 
+// Fused rows: 16 points per thread up to rows of 2^8 points; from 2^9 on,
+// 8, with at most 128 registers (four wavefronts per SIMD).  X's spectrum
+// is held in registers across Y's transform, and with 16 points per thread
+// the long rows need about 170 registers (two wavefronts per SIMD): the
+// fused pass of C2's 1024-point rows took 60 us that way, 52 us this way.
+constexpr int fused_loge(int logl) { return logl <= 8 ? loge_for(logl) : 3; }
+constexpr int fused_rows_per_wg(int logl) {
+  return (kRowThreads >> (logl - fused_loge(logl))) < 1 ? 1 : (kRowThreads >> (logl - fused_loge(logl)));
+}
+
+template <int LOGC>
+static hipError_t rows_fused_l(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                               hipStream_t st) {
+  constexpr int LOGE = fused_loge(LOGC), RPW = fused_rows_per_wg(LOGC);
+  using G = Geometry<LOGC, LOGE>;
+  const size_t lds = ((size_t)RPW * G::STRIDE + (size_t)G::L) * sizeof(uint64_t);
+  auto kern = k_rows_fused<LOGC, LOGE, RPW>;
+  hipError_t e = prepare(kern, lds);
+  if (e != hipSuccess) return e;
+  const uint64_t R = (uint64_t)(sh.rad3 ? 3 : 1) << sh.logR;    // rows of 2^logC points
+  const uint64_t groups = (R + RPW - 1) / RPW;
+  hipLaunchKernelGGL(kern, dim3((unsigned)groups, 2, w.count), dim3(RPW * G::NT), lds, st, w, cs, tw);
+  return hipGetLastError();
+}
+
 template <int LOGR, bool R3>
 static hipError_t inv_cols_launch(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                                   hipStream_t st) {
@@ -483,6 +590,35 @@ hipError_t launch_inverse(const Work& w, const Shape& sh, const Consts& cs, cons
   }
   if (e != hipSuccess) return e;
   if (marks) marks->mark(kInvRows, st);
+  switch (sh.logR) {
+#define X(l) case l: e = inv_cols_l<l>(w, sh, cs, tw, st); break;
+    DMUL_LEN_CASES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+  if (e == hipSuccess && marks) marks->mark(kInvCols, st);
+  return e;
+}
+
+hipError_t launch_fused(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                        const DivTable* dt, hipStream_t st, Marks* marks) {
+  hipError_t e = hipErrorInvalidValue;
+  switch (sh.logR) {
+#define X(l) case l: e = fwd_cols_l<l>(w, sh, cs, tw, dt, st); break;
+    DMUL_LEN_CASES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  if (marks) marks->mark(kFwdCols, st);
+  switch (sh.logC) {
+#define X(l) case l: e = rows_fused_l<l>(w, sh, cs, tw, st); break;
+    DMUL_LEN_CASES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  if (marks) marks->mark(kRows, st);
   switch (sh.logR) {
 #define X(l) case l: e = inv_cols_l<l>(w, sh, cs, tw, st); break;
     DMUL_LEN_CASES(X)
