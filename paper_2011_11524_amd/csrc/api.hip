@@ -282,23 +282,31 @@ int ensure_workspace(dmul_ctx* ctx, size_t words) {
   return DMUL_OK;
 }
 
+// Status words allocated with a context: the single product's and 4096 batch products'.
+constexpr size_t kStatusWords = 4097;
+
 int ensure_status(dmul_ctx* ctx, size_t n) {
   if (ctx->status_cap >= n) return DMUL_OK;
+  // grow by doubling, from room for a 4096-product batch: a larger array
+  // costs a free of the old one, which waits for the whole device
+  size_t cap = ctx->status_cap ? 2 * ctx->status_cap : kStatusWords;
+  while (cap < n) cap *= 2;
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return from_hip(e);
   int* d = nullptr;
-  e = hipMalloc(&d, n * sizeof(int));
+  e = hipMalloc(&d, cap * sizeof(int));
   if (e != hipSuccess) return from_hip(e);
-  e = hipMemset(d, 0, n * sizeof(int));
-  if (e != hipSuccess) { (void)hipFree(d); return from_hip(e); }
-  if (ctx->d_status) {
-    int first = 0;
-    (void)hipMemcpy(&first, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost);
-    (void)hipMemcpy(d, &first, sizeof(int), hipMemcpyHostToDevice);
-    (void)hipFree(ctx->d_status);
+  e = hipMemsetAsync(d, 0, cap * sizeof(int), ctx->stream);
+  if (e == hipSuccess && ctx->d_status)   // the single-product word carries over
+    e = hipMemcpyAsync(d, ctx->d_status, sizeof(int), hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return from_hip(e);
   }
+  if (ctx->d_status) (void)hipFree(ctx->d_status);
   ctx->d_status = d;
-  ctx->status_cap = n;
+  ctx->status_cap = cap;
   return DMUL_OK;
 }
 
@@ -585,7 +593,7 @@ int dmul_ctx_create(dmul_ctx** out, int device, size_t budget) {
   if (e == hipSuccess) e = hipMalloc(&c->d_div, sizeof(DivTable));
   if (e == hipSuccess) e = hipMemcpy(c->d_div, &dt, sizeof(DivTable), hipMemcpyHostToDevice);
   if (e != hipSuccess) rc = from_hip(e);
-  if (!rc) rc = ensure_status(c, 64);
+  if (!rc) rc = ensure_status(c, 1);
 
   if (rc) {
     dmul_ctx_destroy(c);

@@ -36,6 +36,11 @@ int BatchEngine::reserve(dmul_ctx* ctx, size_t ws_words, size_t sync_words, size
   const bool grow = ws_words > ws_words_ || sync_words > sync_words_ || ndesc > desc_cap_;
   if (!grow) return DMUL_OK;
   if (ctx->budget && ws_words * sizeof(uint64_t) > ctx->budget) return DMUL_ENOMEM;
+  // every growth frees buffers (a wait for the whole device): the small
+  // arrays grow by doubling; the workspaces exactly, since they are large
+  // and bounded by the budget
+  if (sync_words > sync_words_) sync_words = std::max(sync_words, 2 * sync_words_);
+  if (ndesc > desc_cap_) ndesc = std::max<size_t>(std::max<size_t>(ndesc, 2 * desc_cap_), 1024);
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return from_hip(e);
   drop_graphs();   // captured batches point into the buffers being replaced

@@ -26,6 +26,7 @@ after an event that orders the two.
 from __future__ import annotations
 
 import ctypes
+import gc
 import time
 from collections import OrderedDict
 from dataclasses import dataclass, field
@@ -232,6 +233,17 @@ class Server:
         {rid: result tensor}."""
         stats = ServeStats()
         self._stats = stats
+        # the cyclic garbage collector, run over the many request objects of
+        # a long stream, pauses the loop for tens of milliseconds at a time
+        gc_was_on = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(reqs, stats, keep_outputs, realtime)
+        finally:
+            if gc_was_on:
+                gc.enable()
+
+    def _run(self, reqs: list, stats: ServeStats, keep_outputs: bool, realtime: bool):
         results = {} if keep_outputs else None
         nxt = 0                      # next request not yet admitted
         t0 = time.perf_counter()
