@@ -176,8 +176,11 @@ int dmul_debug_residues(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint6
  * launches[i] (count) for kernel phase i < n, for products completed by a
  * dmul_sync, and returns the number of phases; dmul_phase_name(i) names
  * phase i ("fwd_cols", "fwd_rows", "inv_rows", "inv_cols", "rec_crt",
- * "rec_apply", and "whole" for the one-workgroup kernel that runs a whole
- * product of transform length N <= 4096). */
+ * "rec_apply", "whole" for the one-workgroup kernel that runs a whole
+ * product of transform length N <= 4096, and "rows" for the pass that runs
+ * the row transforms of both directions and the pointwise product at once,
+ * which products without cached spectra take instead of fwd_rows and
+ * inv_rows). */
 int dmul_ctx_profile(dmul_ctx* ctx, int enable);
 int dmul_ctx_profile_read(dmul_ctx* ctx, double* total_ms, uint64_t* launches, int n);
 /* The kernels of the work completed by the last dmul_sync, in launch order:
