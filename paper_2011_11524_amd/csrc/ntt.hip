@@ -524,7 +524,12 @@ static hipError_t rows_fused_l(const Work& w, const Shape& sh, const Consts& cs,
   if (e != hipSuccess) return e;
   const uint64_t R = (uint64_t)(sh.rad3 ? 3 : 1) << sh.logR;    // rows of 2^logC points
   const uint64_t groups = (R + RPW - 1) / RPW;
-  hipLaunchKernelGGL(kern, dim3((unsigned)groups, 2, w.count), dim3(RPW * G::NT), lds, st, w, cs, tw);
+  // the tuned loop count, within the same launch-size cap as the row passes
+  const uint64_t cap = groups * 2 * w.count / kRowMinGroups;
+  int iters = sh.row_iters > 0 ? sh.row_iters : 1;
+  if ((uint64_t)iters > cap) iters = cap > 1 ? (int)cap : 1;
+  const unsigned gx = (unsigned)((groups + iters - 1) / iters);
+  hipLaunchKernelGGL(kern, dim3(gx, 2, w.count), dim3(RPW * G::NT), lds, st, w, cs, tw);
   return hipGetLastError();
 }
 

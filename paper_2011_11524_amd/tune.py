@@ -7,7 +7,8 @@ candidate launch parameter, and write the fastest choice per class to
 dmul_tune.txt beside the library (read by every new context): lines
 "N row_iters".  The tuned parameter is the number of row groups each
 workgroup of the row pass loops over (1 = one group per workgroup, more =
-fewer, longer-lived workgroups).
+fewer, longer-lived workgroups); batches without cached spectra run the
+fused row pass, so that is the kernel the timings select for.
 
     python -m paper_2011_11524_amd.tune [--min 7] [--max 21] [--out PATH]
 """
