@@ -1,9 +1,10 @@
 // Batched products.  A batch is planned on the host, grouped into size
 // classes by transform length, given one workspace per product, and its
-// descriptors are copied to the device once; then each class runs as six
-// launches (forward columns and rows, inverse rows and columns, the two
-// recovery passes) covering all of its products.  A batch of P products in
-// c classes needs 6c launches instead of 6P.
+// descriptors are copied to the device once; then each class runs as one
+// launch of the whole-product kernel (short lengths), or as five launches
+// (forward columns, the fused rows, inverse columns, the two recovery
+// passes) covering all of its products.  A batch of P products in c
+// classes needs at most 5c launches instead of up to 5P.
 #include <dmul.h>
 
 #include <algorithm>

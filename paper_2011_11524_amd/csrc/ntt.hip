@@ -7,6 +7,10 @@
 //             pass B  C-point DIF on every row
 //   inverse:  pass B  pointwise REDC(X, Y), C-point DIT on every row
 //             pass A  x *= xi_N^(-k1*n2) * R^2 N^-1, R-point DIT on every column
+// The forward pass B, the pointwise product and the inverse pass B act on
+// each row alone, so a product whose operands are both transformed here
+// runs them as one kernel (k_rows_fused); the separate row kernels serve
+// cached transforms (spectra), which must be stored between the two.
 // DIF leaves its outputs in bit-reversed order and DIT consumes that order,
 // so no bit reversal and no transposition is ever done (Sections 5.4, 7.4);
 // a row of C = 3M points runs a length-3 DFT across its thirds first (DIF)

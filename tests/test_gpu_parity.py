@@ -169,6 +169,10 @@ def test_radix3_lengths_vs_oracle(dm, ctx, e):
     got = _gpu_mul(dm, ctx, a, b)
     np.testing.assert_array_equal(got, oracle.mul_ntt(a, b))
     np.testing.assert_array_equal(_gpu_mul(dm, ctx, a, b, pow2=True), got)
+    # a squared from one buffer: one operand transformed, the row pass's
+    # squaring branch, at the length a*a plans to
+    sq = _gpu_mul(dm, ctx, a, a)
+    np.testing.assert_array_equal(sq, oracle.mul_ntt(a, a))
 
 
 def _small_classes():
