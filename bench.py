@@ -366,6 +366,27 @@ def main() -> int:
     ctx.sync()
     prof = ctx.profile_read()
     ctx.profile(False)
+    # host-inclusive rate (reported beside the value, never as it): the
+    # operands start in pinned host memory, and every step copies them in,
+    # multiplies, and copies the product back, all on the context's stream
+    ha = torch.from_numpy(a.view(np.int64)).pin_memory()
+    hb = torch.from_numpy(b.view(np.int64)).pin_memory()
+    hout = torch.empty(len(a) + len(b), dtype=torch.int64).pin_memory()
+    steps_h = max(3, args.steps // 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps_h):
+        ta.view(torch.int64).copy_(ha, non_blocking=True)
+        tb.view(torch.int64).copy_(hb, non_blocking=True)
+        ctx.mul_async(ta, tb, out, pow2=args.pow2)
+        hout.copy_(out.view(torch.int64), non_blocking=True)
+    ctx.sync()
+    torch.cuda.synchronize()
+    el_h = (time.perf_counter() - t0) / steps_h
+    host_inclusive = {"ms_per_product": round(el_h * 1e3, 4), "digits_per_s": 2 * D / el_h,
+                      "bytes_over_pcie": 8 * 2 * (len(a) + len(b)),
+                      "result_matches_device_copy": bool(np.array_equal(hout.numpy().view(np.uint64),
+                                                                        out.cpu().numpy()))}
     NP = pl.groups_a + pl.groups_b
     work = phase_work(pl.N, pl.log2_rows, pl.log2_cols, pl.factor, 4, NP, len(a), len(b))
     phases = {}
@@ -412,6 +433,7 @@ def main() -> int:
                    "seeds": [2001, 2002]},
         "roofline": roofline,
         "hbm": hbm,
+        "host_inclusive": host_inclusive,
         "phases": {k: {kk: round(vv, 3) if isinstance(vv, float) else vv for kk, vv in v.items()}
                    for k, v in phases.items()},
     }
