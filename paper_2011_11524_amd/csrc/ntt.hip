@@ -108,6 +108,9 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
     const int q = threadIdx.x + s * NTH;
     v[s] = q < R * T ? lds[(q % T) * G::STRIDE + lds_pos<LOGE>(q / T)] : 0;
   }
+  // those reads cross columns: every thread has its copy before the first
+  // round of any column's transform overwrites the tile
+  __syncthreads();
   const int col = threadIdx.x / G::NT, t = threadIdx.x % G::NT;
 #pragma unroll 1
   for (int pi = 0; pi < 2; ++pi) {
