@@ -142,6 +142,7 @@ k_rec_apply(Work w, RecTable rt, const DivTable* __restrict__ dt_g) {
   __shared__ DivTable sdt;
   for (unsigned i = threadIdx.x; i < sizeof(DivTable) / 4; i += blockDim.x)
     reinterpret_cast<uint32_t*>(&sdt)[i] = reinterpret_cast<const uint32_t*>(dt_g)[i];
+  __syncthreads();   // the table is written by some threads and read by all
   const DivTable* dt = &sdt;
   const uint64_t B = rc.B;
   const uint64_t k = (uint64_t)rc.k;

@@ -49,6 +49,7 @@ k_small(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g, Rec
   __shared__ DivTable sdt;
   for (unsigned i = threadIdx.x; i < sizeof(DivTable) / 4; i += blockDim.x)
     reinterpret_cast<uint32_t*>(&sdt)[i] = reinterpret_cast<const uint32_t*>(dt_g)[i];
+  __syncthreads();   // the table is written by some threads and read by all
   const DivTable* dt = &sdt;
   const ProdDesc d = load_desc(w);
   const RecConsts rc = rec_consts(rt, d);
