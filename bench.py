@@ -193,8 +193,18 @@ def run_batched(dm, ctx, torch, steps: int, warmup: int, count: int):
     same = all(torch.equal(x, y) for x, y in zip(outs_a, outs_b))
     rng = np.random.default_rng(4007)
     sample = rng.choice(count, size=min(12, count), replace=False)
-    ok = all(np.array_equal(outs_b[i].cpu().numpy(), oracle.mul_ntt(*host[i])) for i in sample)
+    ok, t_or, d_or = True, 0.0, 0
+    for i in sample:
+        t0 = time.perf_counter()
+        want = oracle.mul_ntt(*host[i])
+        t_or += time.perf_counter() - t0
+        d_or += int(da[i]) + int(db[i])
+        ok = ok and np.array_equal(outs_b[i].cpu().numpy(), want)
     res["parity"] = "bit-exact" if (same and ok) else "MISMATCH"
+    # the oracle on the checked sample, single thread: its rate against the
+    # batched GPU rate (context, not a target)
+    res["cpu_oracle_sample"] = {"products": len(sample), "digits": d_or, "seconds": t_or,
+                                "digits_per_s": d_or / t_or if t_or > 0 else None, "cores": 1}
     return res
 
 

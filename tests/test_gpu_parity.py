@@ -459,6 +459,55 @@ def test_batch_graph_replays_match(dm):
         ctx.close()
 
 
+def test_concurrent_repeats_every_kernel_family(dm):
+    """Products that cover every kernel family (one-workgroup batches,
+    column passes with wavefront-owned and workgroup-owned columns, the
+    1024-thread forward tile of 2048-row columns, the fused row pass at 8
+    and 16 points per thread, both recovery forms) enqueued on two contexts
+    with their own streams at once, four times over: every result equals
+    the oracle's.  Waves of different workgroups then run out of step, which
+    is where a missing barrier shows."""
+    import torch
+    _note("concurrent repeats")
+    rng = np.random.default_rng(8080)
+    sizes = [(3000, 2000, False), (60000, 45000, False), (20000, 20000, True),
+             (300000, 250000, False), (1300000, 900000, True)]
+    cases = []
+    for na, nb, pow2 in sizes:
+        a = rng.integers(0, 10 ** 19, size=na, dtype=np.uint64)
+        b = rng.integers(0, 10 ** 19, size=nb, dtype=np.uint64)
+        cases.append((dm.to_device(a), dm.to_device(b), pow2, oracle.mul_ntt(a, b)))
+    small = []
+    for _ in range(16):
+        a = rng.integers(0, 10 ** 19, size=int(rng.integers(100, 700)), dtype=np.uint64)
+        b = rng.integers(0, 10 ** 19, size=int(rng.integers(100, 700)), dtype=np.uint64)
+        small.append((dm.to_device(a), dm.to_device(b), oracle.mul_ntt(a, b)))
+    ctxs = [dm.Context(0, stream=torch.cuda.Stream()) for _ in range(2)]
+    try:
+        for rep in range(4):
+            singles, batches = [], []
+            for c in ctxs:
+                for da, db, pow2, want in cases:
+                    o = torch.empty(da.numel() + db.numel(), dtype=torch.uint64, device="cuda")
+                    c.mul_async(da, db, o, pow2=pow2)
+                    singles.append((o, want))
+                outs = [torch.empty(x.numel() + y.numel(), dtype=torch.uint64, device="cuda")
+                        for x, y, _ in small]
+                st = c.batch_async([(x, y) for x, y, _ in small], outs)
+                batches.append((outs, st))
+            for c in ctxs:
+                c.sync()
+            for o, want in singles:
+                np.testing.assert_array_equal(dm.to_host(o), want, err_msg=f"rep {rep}")
+            for outs, st in batches:
+                assert [int(v) for v in st] == [0] * len(small)
+                for o, (_, _, want) in zip(outs, small):
+                    np.testing.assert_array_equal(dm.to_host(o), want, err_msg=f"rep {rep} batch")
+    finally:
+        for c in ctxs:
+            c.close()
+
+
 def test_context_budget_enomem(dm):
     """A context's workspace budget: a product needing more gets DMUL_ENOMEM
     (single product) or that status per product (batch); products within it
