@@ -26,11 +26,38 @@ void BatchEngine::drop_graphs() {
 
 BatchEngine::~BatchEngine() {
   drop_graphs();
+  for (int i = 0; i < kSideStreams; ++i) {
+    if (side_[i]) (void)hipStreamDestroy(side_[i]);
+    if (join_[i]) (void)hipEventDestroy(join_[i]);
+  }
+  if (fork_) (void)hipEventDestroy(fork_);
   if (ws_) (void)hipFree(ws_);
   if (sync_) (void)hipFree(sync_);
   if (d_desc_) (void)hipFree(d_desc_);
   if (h_desc_) (void)hipHostFree(h_desc_);
   if (copied_) (void)hipEventDestroy(copied_);
+}
+
+int BatchEngine::ensure_side_streams() {
+  if (fork_) return DMUL_OK;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < kSideStreams && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&side_[i], hipStreamNonBlocking);   // default priority
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join_[i], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&fork_, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    for (int i = 0; i < kSideStreams; ++i) {
+      if (side_[i]) (void)hipStreamDestroy(side_[i]);
+      if (join_[i]) (void)hipEventDestroy(join_[i]);
+      side_[i] = nullptr;
+      join_[i] = nullptr;
+    }
+    if (fork_) (void)hipEventDestroy(fork_);
+    fork_ = nullptr;
+    return from_hip(e);
+  }
+  return DMUL_OK;
 }
 
 int BatchEngine::reserve(dmul_ctx* ctx, size_t ws_words, size_t sync_words, size_t ndesc) {
@@ -213,6 +240,8 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
     if (graph) (void)hipFree(descs);
     return from_hip(e);
   }
+  // side streams and events exist before any capture begins
+  const bool fork = !ctx->prof && cls.size() > 1 && ensure_side_streams() == DMUL_OK;
   if (graph) {
     e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
@@ -222,7 +251,18 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
   }
   Marks* marks = ctx->prof;
   if (ctx->prof) ctx->prof->begin(ctx->stream);
+  // classes run concurrently on the side streams (not when profiling, whose
+  // per-kernel events assume one stream)
+  int nside = 0;
+  if (fork) {
+    nside = (int)std::min<size_t>(cls.size(), kSideStreams);
+    e = hipEventRecord(fork_, ctx->stream);
+    for (int i = 0; i < nside && e == hipSuccess; ++i) e = hipStreamWaitEvent(side_[i], fork_, 0);
+    if (e != hipSuccess) nside = 0;
+  }
+  size_t ci = 0;
   for (const Cls& c : cls) {
+    const hipStream_t st = nside ? side_[ci++ % nside] : ctx->stream;
     TwiddleSet tw;
     rc = get_twiddles(ctx, c.p0, &tw);
     if (rc) break;
@@ -232,18 +272,24 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       w.many = descs + c.first + off;
       w.count = (uint32_t)std::min<size_t>(65535, c.n - off);
       if (!c.spectra && small_fits(c.p0, c.n)) {
-        e = launch_small(w, c.sh, ctx->cs, tw, ctx->d_div, &ctx->h_div, ctx->stream, marks);
+        e = launch_small(w, c.sh, ctx->cs, tw, ctx->d_div, &ctx->h_div, st, marks);
         continue;
       }
       if (c.spectra) {
-        e = launch_forward(w, c.sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
-        if (e == hipSuccess) e = launch_inverse(w, c.sh, ctx->cs, tw, ctx->stream, marks);
+        e = launch_forward(w, c.sh, ctx->cs, tw, ctx->d_div, st, marks);
+        if (e == hipSuccess) e = launch_inverse(w, c.sh, ctx->cs, tw, st, marks);
       } else {
-        e = launch_fused(w, c.sh, ctx->cs, tw, ctx->d_div, ctx->stream, marks);
+        e = launch_fused(w, c.sh, ctx->cs, tw, ctx->d_div, st, marks);
       }
-      if (e == hipSuccess) e = launch_recover(w, c.sh, ctx->cs, ctx->d_div, &ctx->h_div, ctx->stream, marks);
+      if (e == hipSuccess) e = launch_recover(w, c.sh, ctx->cs, ctx->d_div, &ctx->h_div, st, marks);
     }
     if (e != hipSuccess) break;
+  }
+  // join: the context stream continues only after every side stream's classes
+  for (int i = 0; i < nside; ++i) {
+    const hipError_t ej = hipEventRecord(join_[i], side_[i]);
+    const hipError_t ew = ej == hipSuccess ? hipStreamWaitEvent(ctx->stream, join_[i], 0) : ej;
+    if (e == hipSuccess) e = ew;
   }
   if (graph) {
     hipGraph_t g = nullptr;

@@ -45,6 +45,16 @@ class BatchEngine {
   };
   std::map<uint64_t, Graph> graphs_;
 
+  // Side streams: the size classes of a batch are independent (own
+  // workspaces, descriptors and status words), so they are dealt to these
+  // streams, forked from and joined back to the context stream by events,
+  // and run concurrently instead of one after another.
+  static constexpr int kSideStreams = 4;
+  int ensure_side_streams();
+  hipStream_t side_[kSideStreams] = {};
+  hipEvent_t fork_ = nullptr;
+  hipEvent_t join_[kSideStreams] = {};
+
   uint64_t* ws_ = nullptr;          // per-product workspaces, back to back
   size_t ws_words_ = 0;
   uint32_t* sync_ = nullptr;        // per-product recovery carry maps
