@@ -12,8 +12,9 @@ Contents
   base-10^19 integers (Section 3.2), in C.
 * ``mul_ntt(a, b, force_k)`` -- O2, the two-prime number-theoretic-transform
   method in its plainest form (Sections 3.2-3.5, 4.2-4.5, 5.1-5.2, 8.2.2),
-  in C: naive '%' reduction, radix-2 decimation in time with an explicit
-  bit-reversal permutation, textbook CRT, sequential carry.
+  in C: naive '%' reduction, the transform of eq. dft by the recursive
+  radix-2 split into even- and odd-indexed terms, textbook CRT, sequential
+  carry.
 * ``is_prime``, ``find_primes``, ``find_primes_for_n``, ``generator``,
   ``transform``, ``choose_k``, ``cyclic_convolution`` -- the pieces the pin
   tests check one by one.

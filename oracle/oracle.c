@@ -15,9 +15,9 @@
  *   O2  oracle_mul_ntt     -- the paper's method taken step by step in its
  *       plainest form: split into base 10^k digit groups (Section 3.2 and the
  *       base choice of Section 4.3), zero-pad to a power of two N >= n+m,
- *       for each of two primes found by FindPrimes (Section 4.5) run the
- *       radix-2 decimation-in-time transform with an explicit bit-reversal
- *       permutation (Section 5.1-5.2, transform tau(A, omega)), multiply
+ *       for each of two primes found by FindPrimes (Section 4.5) compute
+ *       the transform tau(A, omega) of eq. dft by the recursive radix-2
+ *       split into even- and odd-indexed terms (Section 5), multiply
  *       pointwise, transform back with omega^-1 and scale by N^-1
  *       (Section 3.3, eqs. dft/idft and the convolution theorem), recover
  *       each coefficient with the two-prime CRT formula (Section 8.2.2),
@@ -146,22 +146,25 @@ int oracle_is_prime(uint64_t n)
     return 1;
 }
 
-/* FindPrimesForN(n, p_max, l): up to l largest primes c*3*2^n+1 <= p_max
- * with c odd, in decreasing order.  Returns how many were written. */
+/* FindPrimesForN(n, p_max, l) (Section 4.5): up to l largest primes of the
+ * form c*3*2^n + 1 <= p_max with c odd, in decreasing order.  The odd
+ * multipliers c are scanned from the largest one allowed downward.
+ * Returns how many were written. */
 int oracle_find_primes_for_n(int n, uint64_t p_max, int l, uint64_t *res)
 {
     int count = 0;
-    uint64_t psi = (p_max - 1) >> n;
-    if (psi % 2 == 0) psi -= 1;          /* psi = 3c with c odd needs psi odd */
-    while (psi > 0 && psi % 3 != 0) {
-        if (psi < 2) return 0;
-        psi -= 2;
+    uint64_t step, c;
+    if (n < 0 || n > 62 || p_max < 2) return 0;   /* 3 * 2^62 still fits a word */
+    step = 3ULL << n;                          /* p = c * step + 1 */
+    c = (p_max - 1) / step;                    /* largest c with p <= p_max */
+    if (c % 2 == 0) {
+        if (c == 0) return 0;
+        c -= 1;                                /* c must be odd */
     }
-    while (psi > 0 && count < l) {
-        uint64_t p = (psi << n) + 1;
+    for (; count < l; c -= 2) {
+        uint64_t p = c * step + 1;
         if (oracle_is_prime(p)) res[count++] = p;
-        if (psi < 6) break;
-        psi -= 6;
+        if (c < 3) break;                      /* c = 1 was the last odd multiplier */
     }
     return count;
 }
@@ -235,43 +238,47 @@ int oracle_primes(uint64_t *p, uint64_t *g)
 }
 
 /* ------------------------------------------------------------------ */
-/* The transform tau(A, omega) (Section 5): bit-reversal permutation    */
-/* followed by the decimation-in-time stages.                           */
+/* The transform tau(A, omega) (Section 5, eq. dft): A'[k] =            */
+/* sum_i A[i] omega^(ik), by the radix-2 split of the sum into its      */
+/* even- and odd-indexed terms.                                         */
 /* ------------------------------------------------------------------ */
 
-static void bit_reverse_permute(uint64_t *A, size_t len)
+/* out[k], k < len, = sum_t in[t*stride] * w^(t*k), w a primitive len-th
+ * root of unity, len a power of two.  With E and O the transforms of the
+ * even and odd terms (length len/2, root w^2):
+ *   out[k] = E[k] + w^k O[k],  out[k + len/2] = E[k] - w^k O[k]. */
+static void dft_split(const uint64_t *in, size_t stride, uint64_t *out, size_t len,
+                      uint64_t w, uint64_t p)
 {
-    int bits = 0;
-    size_t k;
-    while (((size_t)1 << bits) < len) bits++;
-    for (k = 0; k < len; k++) {
-        size_t r = 0, t = k;
-        int i;
-        for (i = 0; i < bits; i++) { r = (r << 1) | (t & 1); t >>= 1; }
-        if (k < r) { uint64_t x = A[k]; A[k] = A[r]; A[r] = x; }
+    size_t h = len / 2, k;
+    uint64_t wk = 1, w2;
+    if (len == 1) {
+        out[0] = in[0];
+        return;
+    }
+    w2 = mulmod(w, w, p);
+    dft_split(in, 2 * stride, out, h, w2, p);              /* E in out[0, h)   */
+    dft_split(in + stride, 2 * stride, out + h, h, w2, p); /* O in out[h, len) */
+    for (k = 0; k < h; k++) {
+        uint64_t e = out[k];
+        uint64_t o = mulmod(wk, out[k + h], p);
+        out[k] = addmod(e, o, p);
+        out[k + h] = submod(e, o, p);
+        wk = mulmod(wk, w, p);
     }
 }
 
 /* A'[k] = sum_i A[i] omega^(ik) for len a power of two and omega a
- * primitive len-th root of unity mod p. */
+ * primitive len-th root of unity mod p; in place (through a copy). */
 int oracle_transform(uint64_t *A, size_t len, uint64_t p, uint64_t omega)
 {
-    size_t m, k, j;
+    uint64_t *copy;
     if (len == 0 || (len & (len - 1))) return ORACLE_EINVAL;
-    bit_reverse_permute(A, len);
-    for (m = 2; m <= len; m <<= 1) {
-        uint64_t wm = powmod(omega, len / m, p);
-        for (k = 0; k < len; k += m) {
-            uint64_t phi = 1;
-            for (j = 0; j < m / 2; j++) {
-                uint64_t u = A[k + j];
-                uint64_t v = mulmod(phi, A[k + j + m / 2], p);
-                A[k + j] = addmod(u, v, p);
-                A[k + j + m / 2] = submod(u, v, p);
-                phi = mulmod(phi, wm, p);
-            }
-        }
-    }
+    copy = malloc(len * sizeof(uint64_t));
+    if (!copy) return ORACLE_ENOMEM;
+    memcpy(copy, A, len * sizeof(uint64_t));
+    dft_split(copy, 1, A, len, omega, p);
+    free(copy);
     return ORACLE_OK;
 }
 
@@ -410,10 +417,12 @@ int oracle_mul_ntt(const uint64_t *a, size_t na, const uint64_t *b, size_t nb,
         uint64_t xi = powmod(g_gen[j], (p - 1) / N, p);   /* primitive N-th root */
         uint64_t xi_inv = powmod(xi, p - 2, p);
         uint64_t n_inv = powmod(N % p, p - 2, p);
-        oracle_transform(x[j], N, p, xi);
-        oracle_transform(y[j], N, p, xi);
+        if (oracle_transform(x[j], N, p, xi) || oracle_transform(y[j], N, p, xi)) {
+            rc = ORACLE_ENOMEM;
+            goto done;
+        }
         for (i = 0; i < N; i++) x[j][i] = mulmod(x[j][i], y[j][i], p);
-        oracle_transform(x[j], N, p, xi_inv);
+        if (oracle_transform(x[j], N, p, xi_inv)) { rc = ORACLE_ENOMEM; goto done; }
         for (i = 0; i < N; i++) x[j][i] = mulmod(x[j][i], n_inv, p);
     }
 
