@@ -13,8 +13,11 @@ oracle afterwards.
 Printed: one JSON line with the metric (decimal digits multiplied per
 second), the ALU roofline of the dominant kernel (per-kernel HIP-event
 durations on the launch stream), the algorithmic HBM rate of the NTT phases,
-the CPU oracle timed on this host, and (with --batched) the batched
-workload against one launch per product.
+the CPU oracle timed on this host (one thread, and every core), and the two
+further workloads of the metric (skipped with --no-batched/--no-serving):
+4096 batched products against one launch set per product, with p50/p99
+completion latency of both, and a 100k-request Poisson serving stream with
+p50/p99 latency and digits/s; each with its own parity check.
 """
 from __future__ import annotations
 
@@ -118,51 +121,89 @@ def _pct(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else None
 
 
-def run_batched(dm, ctx, torch, steps: int, warmup: int, count: int):
+def _oracle_rates(jobs, budget_s: float):
+    """The oracle on a list of (label, a, b, digits) jobs: single-thread in
+    order until budget_s is spent, then the same products spread over every
+    host core (the oracle's C code runs outside the interpreter lock).
+    Returns ({label: result}, single-thread stats, all-cores stats)."""
+    import concurrent.futures
+    import oracle
+    got, t1, d1 = {}, 0.0, 0
+    for lab, a, b, d in jobs:
+        if t1 >= budget_s:
+            break
+        t0 = time.perf_counter()
+        got[lab] = oracle.mul_ntt(a, b)
+        t1 += time.perf_counter() - t0
+        d1 += d
+    done = [j for j in jobs if j[0] in got]
+    threads = max(1, min(16, len(os.sched_getaffinity(0)), len(done)))
+    t0 = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        par = list(ex.map(lambda j: oracle.mul_ntt(j[1], j[2]), done))
+    tp = time.perf_counter() - t0
+    import numpy as np
+    same = all(np.array_equal(x, got[j[0]]) for x, j in zip(par, done))
+    single = {"products": len(done), "digits": d1, "seconds": t1, "cores": 1,
+              "digits_per_s": d1 / t1 if t1 > 0 else None}
+    allc = {"products": len(done), "digits": d1, "seconds": tp, "cores": threads,
+            "digits_per_s": d1 / tp if tp > 0 else None, "same_as_single_thread": bool(same)}
+    return got, single, allc
+
+
+def run_batched(dm, torch, steps: int, warmup: int, count: int, oracle_budget_s: float = 6.0):
     """The batched workload: `count` products, operand lengths log-uniform in
     [10^3, 10^6] digits with an aspect ratio uniform in [1, 4], uniform
-    digits; one dmul_batch (one launch per phase and size class) against one
-    dmul_ex per product.  Throughput from K timed repetitions; completion
-    latency of every product (from the first kernel of the batch, events on
-    the launch stream) from one profiled repetition of each mode."""
+    digits; one dmul_batch (one launch per phase and size class, classes
+    concurrent on side streams) against one dmul_ex per product.
+
+    Throughput from K timed repetitions of each mode.  Completion latency of
+    every product -- all `count` requested at once, each complete when its
+    result is -- from one more repetition of the plain and the eager
+    batched modes with completion events (dmul_ctx_timing), which keep the
+    batch's concurrent schedule.  Every mode writes its own outputs; each is
+    compared with the plain results, and a seeded sample with the oracle."""
     import numpy as np
-    import oracle
     import synth
     da, db = synth.batched_lengths(count)
     pool = synth.OperandPool(10 ** 6, seed=4006, pool_limbs=4 * synth.limbs_for_digits(10 ** 6))
-    host, pairs, outs_a, outs_b, digits = [], [], [], [], 0
+    host, pairs, digits = [], [], 0
     for x, y in zip(da, db):
         a = pool.take(int(x))
         b = pool.take(int(y))
         host.append((a, b))
         pairs.append((dm.to_device(a), dm.to_device(b)))
-        outs_a.append(torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda"))
-        outs_b.append(torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda"))
         digits += int(x) + int(y)
     lens = [dm.plan(len(a), len(b)).N for a, b in host]
-
-    def one_by_one():
-        for (ta, tb), o in zip(pairs, outs_a):
-            ctx.mul_async(ta, tb, o)
-        ctx.sync()
-
-    prepared = ctx.prepare_batch(pairs, outs_b)     # marshalled once, submitted every step
-
-    def batched():
-        st = ctx.run_prepared(prepared)
-        ctx.sync()
-        return st
-
-    def batched_graph():
-        st = gctx.run_prepared(prepared, graph=True)
-        gctx.sync()
-        return st
-
+    new_outs = lambda: [torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda") for a, b in host]
+    outs = {m: new_outs() for m in ("per_product", "batched", "batched_graph", "latency_per_product",
+                                    "latency_batched")}
+    ctx = dm.Context(0, stream=torch.cuda.Stream())
     gctx = dm.Context(0, stream=torch.cuda.Stream())
+    statuses = []
 
+    def one_by_one(o):
+        def f():
+            for (ta, tb), z in zip(pairs, o):
+                ctx.mul_async(ta, tb, z)
+            ctx.sync()
+        return f
+
+    def batched(c, pb, graph):
+        def f():
+            st = c.run_prepared(pb, graph=graph)
+            c.sync()
+            statuses.append(list(st))
+        return f
+
+    prepared = {m: ctx.prepare_batch(pairs, outs[m]) for m in ("batched", "latency_batched")}
+    prepared["batched_graph"] = gctx.prepare_batch(pairs, outs["batched_graph"])
+    modes = (("per_product", one_by_one(outs["per_product"])),
+             ("batched", batched(ctx, prepared["batched"], False)),
+             ("batched_graph", batched(gctx, prepared["batched_graph"], True)))
     res = {"products": count, "digits": digits,
            "size_classes": {int(k): int(v) for k, v in zip(*np.unique(lens, return_counts=True))}}
-    for name, fn in (("per_product", one_by_one), ("batched", batched), ("batched_graph", batched_graph)):
+    for name, fn in modes:
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
@@ -172,55 +213,46 @@ def run_batched(dm, ctx, torch, steps: int, warmup: int, count: int):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         res[name] = {"ms_per_batch": dt * 1e3, "digits_per_s": digits / dt}
-    # completion latency of every product, one profiled repetition per mode
-    ctx.profile(True)
-    one_by_one()
-    ev = [t for ph, t in ctx.profile_events() if ph in ("rec_apply", "whole")]
-    lat_pp = ev[:count]
-    batched()
-    ev = [t for ph, t in ctx.profile_events() if ph in ("rec_apply", "whole")]
-    ctx.profile(False)
-    classes = sorted(set(lens))
-    done = {c: ev[i] for i, c in enumerate(classes)} if len(ev) == len(classes) else {}
-    lat_b = [done[c] for c in lens] if done else []
+    # completion latency in the timed schedules (concurrent class streams for
+    # the batch, one stream for one launch set per product)
+    ctx.timing(True)
+    one_by_one(outs["latency_per_product"])()
+    lat_pp = ctx.timing_read()
+    batched(ctx, prepared["latency_batched"], False)()
+    lat_b = ctx.timing_read()
+    ctx.timing(False)
     for name, lat in (("per_product", lat_pp), ("batched", lat_b)):
-        res[name]["p50_ms"] = _pct(lat, 50)
-        res[name]["p99_ms"] = _pct(lat, 99)
-    gctx.close()
+        ok = len(lat) == count and min(lat) >= 0
+        res[name]["p50_ms"] = _pct(lat, 50) if ok else None
+        res[name]["p99_ms"] = _pct(lat, 99) if ok else None
+        res[name]["max_ms"] = max(lat) if ok else None
+    res["latency_mode"] = ("completion events on the launch streams: eager batch with its classes "
+                           "on concurrent side streams, and one launch set per product on one stream")
     res["speedup"] = res["per_product"]["ms_per_batch"] / res["batched"]["ms_per_batch"]
     res["speedup_graph"] = res["per_product"]["ms_per_batch"] / res["batched_graph"]["ms_per_batch"]
-    # every batched result equals its per-product result; a sample against the oracle
-    same = all(torch.equal(x, y) for x, y in zip(outs_a, outs_b))
+    # parity: every mode equals the plain results; a seeded sample equals the oracle
+    ref = outs["per_product"]
+    mode_same = {m: all(torch.equal(x, y) for x, y in zip(ref, o)) for m, o in outs.items()
+                 if m != "per_product"}
+    status_ok = all(all(v == 0 for v in st) for st in statuses)
     rng = np.random.default_rng(4007)
-    sample = rng.choice(count, size=min(48, count), replace=False)
-    ok, t_or, d_or = True, 0.0, 0
-    for i in sample:
-        t0 = time.perf_counter()
-        want = oracle.mul_ntt(*host[i])
-        t_or += time.perf_counter() - t0
-        d_or += int(da[i]) + int(db[i])
-        ok = ok and np.array_equal(outs_b[i].cpu().numpy(), want)
-    # the same sample with the products spread over every host core (the
-    # oracle's C code runs outside the interpreter lock)
-    import concurrent.futures
-    import os
-    threads = max(1, min(16, len(os.sched_getaffinity(0)), len(sample)))
-    t0 = time.perf_counter()
-    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
-        par = list(ex.map(lambda i: oracle.mul_ntt(*host[i]), sample))
-    t_par = time.perf_counter() - t0
-    ok = ok and all(np.array_equal(outs_b[i].cpu().numpy(), w) for i, w in zip(sample, par))
-    res["parity"] = "bit-exact" if (same and ok) else "MISMATCH"
-    # the oracle on the checked sample: its rate against the batched GPU rate
-    # (context, not a target)
-    res["cpu_oracle_sample"] = {"products": len(sample), "digits": d_or, "seconds": t_or,
-                                "digits_per_s": d_or / t_or if t_or > 0 else None, "cores": 1}
-    res["cpu_oracle_sample_all_cores"] = {"products": len(sample), "seconds": t_par, "cores": threads,
-                                          "digits_per_s": d_or / t_par if t_par > 0 else None}
+    sample = [int(i) for i in rng.choice(count, size=min(64, count), replace=False)]
+    jobs = [(i, host[i][0], host[i][1], int(da[i]) + int(db[i])) for i in sample]
+    want, single, allc = _oracle_rates(jobs, oracle_budget_s)
+    oracle_ok = all(np.array_equal(ref[i].cpu().numpy(), w) for i, w in want.items())
+    res["parity"] = "bit-exact" if (all(mode_same.values()) and oracle_ok and status_ok and want) \
+        else "MISMATCH"
+    res["parity_detail"] = {"modes_equal_plain": mode_same, "statuses_ok": status_ok,
+                            "oracle_sample_products": len(want), "oracle_sample_equal": oracle_ok}
+    # the oracle on the checked sample (context, not a target)
+    res["cpu_oracle_sample"] = single
+    res["cpu_oracle_sample_all_cores"] = allc
+    ctx.close()
+    gctx.close()
     return res
 
 
-def run_serving(dm, torch, count: int, seed: int = 5005):
+def run_serving(dm, torch, count: int, seed: int = 5005, oracle_budget_s: float = 6.0):
     """The serving workload: `count` requests, each operand length
     round(10^U(2, 7)) digits, Poisson arrivals at 70% of the device's service
     rate (measured on a calibration draw served back to back), operands
@@ -257,15 +289,24 @@ def run_serving(dm, torch, count: int, seed: int = 5005):
     finally:
         srv.close()
     ctx = dm.Context(0)
-    same = True
+    same = len(mixed) == len(sample)
     for k, r in enumerate(sample):
         alone = ctx.mul(pool[r.a_off: r.a_off + r.na].contiguous(), pool[r.b_off: r.b_off + r.nb].contiguous())
         same = same and torch.equal(alone, mixed[k])
     ctx.close()
+    # the oracle on a seeded part of the sample (as many as oracle_budget_s allows)
+    jobs = [(k, pool_h[r.a_off: r.a_off + r.na], pool_h[r.b_off: r.b_off + r.nb], r.digits())
+            for k, r in enumerate(sample)]
+    want, single, allc = _oracle_rates(jobs, oracle_budget_s)
+    oracle_ok = bool(want) and all(np.array_equal(mixed[k].cpu().numpy(), w) for k, w in want.items())
     out = stats.summary()
     out.update({"service_us_per_request": service * 1e6, "arrival_rate_per_s": rate,
                 "target_load": 0.7, "alone_vs_mix_sample": len(sample),
-                "alone_vs_mix": "identical" if same else "DIFFERENT"})
+                "alone_vs_mix": "identical" if same else "DIFFERENT",
+                "oracle_sample_products": len(want), "oracle_sample": "equal" if oracle_ok else "MISMATCH",
+                "parity": "bit-exact" if (same and oracle_ok and not stats.failed) else "MISMATCH",
+                "cpu_oracle_sample": single, "cpu_oracle_sample_all_cores": allc,
+                "digits_counted": "requested decimal digits of both operands"})
     return out
 
 
@@ -332,9 +373,9 @@ def main() -> int:
     ap.add_argument("--force-k", type=int, default=0, help="digit-group size to force (13..18)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time at most")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batched", action="store_true", help="also run the batched workload")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 4096-product batched workload")
     ap.add_argument("--batch-count", type=int, default=4096)
-    ap.add_argument("--serving", action="store_true", help="also run the serving workload")
+    ap.add_argument("--no-serving", action="store_true", help="skip the 100k-request serving workload")
     ap.add_argument("--requests", type=int, default=100_000)
     ap.add_argument("--serving-hot", type=float, default=0.0,
                     help="also serve a mix where this fraction of requests reuses 32 hot operands, "
@@ -469,10 +510,12 @@ def main() -> int:
                    for k, v in phases.items()},
     }
 
-    if args.batched:
-        result["batched"] = run_batched(dm, ctx, torch, max(2, args.steps // 5), 1, args.batch_count)
+    if not args.no_batched:
+        print(f"[bench] batched workload: {args.batch_count} products", flush=True)
+        result["batched"] = run_batched(dm, torch, max(2, args.steps // 5), 1, args.batch_count)
         print(f"[bench] batched: {json.dumps(result['batched'])}", flush=True)
-    if args.serving:
+    if not args.no_serving:
+        print(f"[bench] serving workload: {args.requests} requests", flush=True)
         result["serving"] = run_serving(dm, torch, args.requests)
         print(f"[bench] serving: {json.dumps(result['serving'])}", flush=True)
     if args.serving_hot > 0:
@@ -480,6 +523,7 @@ def main() -> int:
         print(f"[bench] serving_hot: {json.dumps(result['serving_hot'])}", flush=True)
 
     if not args.no_cpu_baseline:
+        print("[bench] oracle on the host cores", flush=True)
         want, times = cpu_baseline(a, b, args.cpu_budget, 3)
         cores = 1
         result["cpu_baseline"] = {"value": (D + DB) / (sum(times) / len(times)), "unit": "digits/s",
@@ -487,6 +531,18 @@ def main() -> int:
                                   "sample": f"{len(times)} full {D}x{DB}-digit products by the "
                                             "oracle's plain two-prime NTT, single thread",
                                   "host_cores_available": len(os.sched_getaffinity(0))}
+        # the same product on every host core at once, one product per thread
+        import concurrent.futures
+        import oracle
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        t0 = time.perf_counter()
+        with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+            par = list(ex.map(lambda _: oracle.mul_ntt(a, b), range(threads)))
+        tp = time.perf_counter() - t0
+        result["cpu_baseline_all_cores"] = {
+            "value": threads * (D + DB) / tp, "unit": "digits/s", "cores": threads, "kind": "oracle",
+            "sample": f"{threads} full {D}x{DB}-digit products by the oracle, one per thread, at once",
+            "same_as_single_thread": bool(all(np.array_equal(x, want) for x in par))}
         result["parity"] = "bit-exact" if np.array_equal(got, want) else "MISMATCH"
         if not np.array_equal(got, want):
             print("[bench] MISMATCH against the oracle", file=sys.stderr, flush=True)
@@ -501,7 +557,9 @@ def main() -> int:
 
     ctx.close()
     print(json.dumps(result), flush=True)
-    return 0 if result.get("parity", "bit-exact") == "bit-exact" else 1
+    ok = all(r.get("parity", "bit-exact") == "bit-exact"
+             for r in (result, result.get("batched", {}), result.get("serving", {})))
+    return 0 if ok else 1
 
 
 if __name__ == "__main__":

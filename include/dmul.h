@@ -135,7 +135,9 @@ int dmul_sync(dmul_ctx* ctx);
  * into one launch per phase and transform length (so a batch needs a fixed
  * number of launches, not one set per product); dmul_sync completes it.
  * status[i] (host memory, written by dmul_sync) receives each product's own
- * code.  Returns DMUL_OK or the first argument error (then nothing is
+ * code; the array must stay valid until that dmul_sync.  Several batches
+ * may be enqueued before one dmul_sync: each reports to its own status
+ * array.  Returns DMUL_OK or the first argument error (then nothing is
  * enqueued).  `flags` as for dmul_ex, applied to every product. */
 int dmul_batch(dmul_ctx* ctx, size_t count, const uint64_t* const* a, const size_t* na,
                const uint64_t* const* b, const size_t* nb, uint64_t* const* out,
@@ -189,6 +191,23 @@ int dmul_ctx_profile_read(dmul_ctx* ctx, double* total_ms, uint64_t* launches, i
  * kernels (fills at most n). */
 int dmul_ctx_profile_events(dmul_ctx* ctx, int32_t* phases, double* end_ms, int n);
 const char* dmul_phase_name(int phase);
+
+/* Completion timing, for latency measurement without changing the
+ * schedule.  dmul_ctx_timing(ctx, 1) makes every later product on the
+ * context record one HIP event when it completes: after each dmul_ex
+ * product on the context stream, and after each transform-length class of
+ * a batch on the stream that class runs on (batches keep running their
+ * classes concurrently; only hipGraph capture is skipped while timing is
+ * on), plus one start event before the first work enqueued after a
+ * dmul_sync.  0 turns it off.  Returns DMUL_OK, DMUL_EINVAL or
+ * DMUL_ENOMEM.
+ * dmul_ctx_timing_read fills ms[i] for i < n with the completion time, in
+ * milliseconds after that start event, of the i-th product (in submission
+ * order: dmul_ex products one by one, batch products in batch order) of
+ * the work completed by the last dmul_sync; -1 where no time was recorded
+ * (an argument error).  Returns the number of products, or DMUL_EINVAL. */
+int dmul_ctx_timing(dmul_ctx* ctx, int enable);
+long dmul_ctx_timing_read(dmul_ctx* ctx, double* ms, size_t n);
 
 /* Cached transforms (transform reuse, the self-convolution idea of
  * Section 6 carried across products): the forward transforms of one operand

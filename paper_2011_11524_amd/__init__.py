@@ -37,7 +37,7 @@ EXPORTS = ("dmul", "dmul_ctx_create", "dmul_ctx_destroy", "dmul_ctx_set_stream",
            "dmul_host", "dmul_primes", "dmul_debug_residues", "dmul_version", "dmul_ctx_profile",
            "dmul_ctx_profile_read", "dmul_phase_name", "dmul_ctx_profile_events", "dmul_ctx_tune",
            "dmul_spectrum_create", "dmul_spectrum_destroy", "dmul_spectrum_bytes", "dmul_ex_spectrum",
-           "dmul_batch_ex")
+           "dmul_batch_ex", "dmul_ctx_timing", "dmul_ctx_timing_read")
 
 
 class DmulError(RuntimeError):
@@ -109,6 +109,9 @@ def lib():
     L.dmul_ctx_profile_events.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     L.dmul_ctx_tune.argtypes = [vp, ctypes.c_uint64, ctypes.c_int]
+    L.dmul_ctx_timing.argtypes = [vp, ctypes.c_int]
+    L.dmul_ctx_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz]
+    L.dmul_ctx_timing_read.restype = ctypes.c_long
     L.dmul_spectrum_create.argtypes = [vp, vp, sz, sz, ctypes.c_uint, vp, sz, ctypes.POINTER(vp)]
     L.dmul_spectrum_destroy.argtypes = [vp]
     L.dmul_spectrum_bytes.argtypes = [sz, sz, ctypes.c_uint]
@@ -195,6 +198,7 @@ class Context:
 
     def __init__(self, device: int = 0, budget_bytes: int = 0, stream=None):
         self._lib = lib()
+        self._pending = []          # batches enqueued since the last sync
         h = ctypes.c_void_p()
         rc = self._lib.dmul_ctx_create(ctypes.byref(h), int(device), int(budget_bytes))
         if rc:
@@ -242,6 +246,8 @@ class Context:
 
     def sync(self) -> None:
         rc = self._lib.dmul_sync(self._h)
+        # the status arrays of the batches this sync completed have been filled
+        self._pending = []
         if rc:
             raise DmulError(rc, "dmul_sync")
 
@@ -313,6 +319,9 @@ class Context:
             rc = self._lib.dmul_batch(self._h, pb.n, pb.A, pb.NA, pb.B, pb.NB, pb.O, pb.st, flags)
         if rc:
             raise DmulError(rc, "dmul_batch")
+        # the library writes pb.st at the next sync: keep it (and the
+        # batch's tensors) alive until then
+        self._pending.append(pb)
         return pb.st
 
     def batch_async(self, pairs: Sequence, outs: Sequence, force_k: int = 0, graph: bool = False,
@@ -323,9 +332,7 @@ class Context:
         batch in a HIP graph, replayed when the same batch is submitted
         again."""
         pb = PreparedBatch(pairs, outs)
-        st = self.run_prepared(pb, force_k, graph, pow2)
-        self._keep = pb
-        return st
+        return self.run_prepared(pb, force_k, graph, pow2)
 
     def batch(self, pairs: Sequence, force_k: int = 0, graph: bool = False, outs=None,
               pow2: bool = False):
@@ -367,6 +374,24 @@ class Context:
         t = (ctypes.c_double * n)()
         self._lib.dmul_ctx_profile_events(self._h, ph, t, n)
         return [(self._lib.dmul_phase_name(ph[i]).decode(), float(t[i])) for i in range(n)]
+
+    # -- completion timing ---------------------------------------------------
+    def timing(self, enable: bool) -> None:
+        """Per-product completion events (batches keep their concurrent
+        class streams; graph capture is skipped while on)."""
+        rc = self._lib.dmul_ctx_timing(self._h, 1 if enable else 0)
+        if rc:
+            raise DmulError(rc, "dmul_ctx_timing")
+
+    def timing_read(self) -> list:
+        """Completion ms of every product of the work completed by the last
+        sync (submission order), after the first of that work's start."""
+        n = self._lib.dmul_ctx_timing_read(self._h, None, 0)
+        if n < 0:
+            raise DmulError(n, "dmul_ctx_timing_read")
+        ms = (ctypes.c_double * max(n, 1))()
+        self._lib.dmul_ctx_timing_read(self._h, ms, n)
+        return [float(ms[i]) for i in range(n)]
 
     # -- debug view of the convolution ---------------------------------------
     def residues(self, a, b, force_k: int = 0, pow2: bool = False):

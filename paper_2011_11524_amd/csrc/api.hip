@@ -135,6 +135,15 @@ hipError_t allow_lds(const void* kernel, size_t lds_bytes) {
 
 int from_hip(hipError_t e) { return e == hipSuccess ? DMUL_OK : (e == hipErrorOutOfMemory ? DMUL_ENOMEM : DMUL_EDEVICE); }
 
+// Rows of the R x C layout of a length 2^e (rad3 = 0) or 3 * 2^e (rad3 = 1):
+// R = 2^floor(e/2) (Section 7.9), with fewer columns for 3 * 2^e where a
+// row would pass 3 * 2^kMaxLogC3 points.
+int layout_logR(int e, int rad3) {
+  int r = e / 2;
+  if (rad3 && e - r > kMaxLogC3) r = e - kMaxLogC3;
+  return r;
+}
+
 int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl) {
   if (flags & ~(DMUL_FLAG_K_MASK | DMUL_FLAG_POW2)) return DMUL_EINVAL;
   const int fk = (int)(flags & DMUL_FLAG_K_MASK);
@@ -172,8 +181,7 @@ int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl) {
   while (((uint64_t)1 << e2) < need) ++e2;
   int e3 = kMinLogN3;
   while (((uint64_t)3 << e3) < need) ++e3;
-  int logR3 = e3 / 2;
-  if (e3 - logR3 > kMaxLogC3) logR3 = e3 - kMaxLogC3;
+  const int logR3 = layout_logR(e3, 1);
   const bool fit3 = logR3 <= kMaxLogR3;
   const bool fit2 = e2 <= kMaxLogN;
   const bool use3 = !(flags & DMUL_FLAG_POW2) && fit3 && (!fit2 || ((uint64_t)3 << e3) < ((uint64_t)1 << e2));
@@ -192,7 +200,7 @@ int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl) {
     pl->rad3 = 0;
     pl->logN = e2;
     pl->N = (uint64_t)1 << e2;
-    pl->logR = e2 / 2;
+    pl->logR = layout_logR(e2, 0);
   }
   pl->logC = pl->logN - pl->logR;
   return DMUL_OK;
@@ -200,10 +208,48 @@ int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl) {
 
 size_t workspace_words(const PlanDev& pl) { return 4 * (size_t)pl.N; }
 
-// Builds (once per length) the inter-pass factor tables of a transform of
-// length N = R*C and returns pointers to them: xi_N^(+-e) for e < N as
-// hi[e >> lb] * lo[e mod 2^lb], lb = pass_split_bits.
-int get_twiddles(dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw) {
+// Inter-pass factor tables of a transform of length N = R*C with split bits
+// lb (Section 7.9's twiddle xi_N^(+-e), e < N, as hi[e >> lb] * lo[e mod 2^lb];
+// the inverse low table also carries R^2 N^-1, Section 6), in Montgomery
+// form: 2 * (HI + LO) words per prime, written to h.  scale[] receives
+// R^2 N^-1 in Montgomery form per prime.
+static size_t pass_words(uint64_t N, int lb) {
+  return 2 * 2 * ((size_t)(N >> lb) + ((size_t)1 << lb));
+}
+
+static void fill_pass_tables(uint64_t N, int lb, uint64_t* h, uint64_t scale[2]) {
+  const size_t LO = (size_t)1 << lb, HI = N >> lb;
+  const size_t per = 2 * (HI + LO);
+  for (int i = 0; i < 2; ++i) {
+    const uint64_t p = kP[i];
+    const uint64_t xi = powmod(kG[i], (p - 1) / N, p);   // primitive N-th root
+    const uint64_t xinv = inv_mod(xi, p);
+    const uint64_t rn = mulmod(to_mont(1, p), inv_mod(N % p, p), p);   // R * N^-1
+    uint64_t* hf = h + (size_t)i * per;
+    uint64_t* lf = hf + HI;
+    uint64_t* hi = lf + LO;
+    uint64_t* li = hi + HI;
+    const uint64_t xiS = powmod(xi, LO, p), xinvS = powmod(xinv, LO, p);
+    uint64_t a = 1, b = 1;
+    for (size_t e = 0; e < HI; ++e) {
+      hf[e] = to_mont(a, p);
+      hi[e] = to_mont(b, p);
+      a = mulmod(a, xiS, p);
+      b = mulmod(b, xinvS, p);
+    }
+    a = 1;
+    b = 1;
+    for (size_t e = 0; e < LO; ++e) {
+      lf[e] = to_mont(a, p);
+      li[e] = to_mont(mulmod(b, rn, p), p);
+      a = mulmod(a, xi, p);
+      b = mulmod(b, xinv, p);
+    }
+    scale[i] = to_mont(rn, p);
+  }
+}
+
+static void set_twiddles(const dmul_ctx* ctx, const PlanDev& pl, const PassTables& pt, TwiddleSet* tw) {
   const size_t L1 = ((size_t)1 << kMaxLogLen) - 1;
   for (int i = 0; i < 2; ++i) {
     tw->len_fwd[i] = ctx->d_roots + (size_t)(2 * i) * L1;
@@ -212,57 +258,43 @@ int get_twiddles(dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw) {
     tw->r3_inv[i] = ctx->d_r3 + (size_t)(2 * i + 1) * kR3TableWords;
   }
   const int lb = pass_split_bits(pl.logC, pl.rad3);
-  const size_t N = pl.N, LO = (size_t)1 << lb, HI = N >> lb;
+  const size_t LO = (size_t)1 << lb, HI = pl.N >> lb;
   const size_t per = 2 * (HI + LO);
-  auto it = ctx->pass.find(N);
-  if (it == ctx->pass.end()) {
-    std::vector<uint64_t> h(2 * per);
-    for (int i = 0; i < 2; ++i) {
-      const uint64_t p = kP[i];
-      const uint64_t xi = powmod(kG[i], (p - 1) / N, p);   // primitive N-th root
-      const uint64_t xinv = inv_mod(xi, p);
-      const uint64_t scale = mulmod(to_mont(1, p), inv_mod(N % p, p), p);   // R * N^-1
-      uint64_t* hf = h.data() + (size_t)i * per;
-      uint64_t* lf = hf + HI;
-      uint64_t* hi = lf + LO;
-      uint64_t* li = hi + HI;
-      const uint64_t xiS = powmod(xi, LO, p), xinvS = powmod(xinv, LO, p);
-      uint64_t a = 1, b = 1;
-      for (size_t e = 0; e < HI; ++e) {
-        hf[e] = to_mont(a, p);
-        hi[e] = to_mont(b, p);
-        a = mulmod(a, xiS, p);
-        b = mulmod(b, xinvS, p);
-      }
-      a = 1;
-      b = 1;
-      for (size_t e = 0; e < LO; ++e) {
-        lf[e] = to_mont(a, p);
-        li[e] = to_mont(mulmod(b, scale, p), p);
-        a = mulmod(a, xi, p);
-        b = mulmod(b, xinv, p);
-      }
-    }
-    PassTables pt;
-    for (int i = 0; i < 2; ++i)
-      pt.scale[i] = to_mont(mulmod(to_mont(1, kP[i]), inv_mod(N % kP[i], kP[i]), kP[i]), kP[i]);
-    hipError_t e = hipMalloc(&pt.dev, h.size() * sizeof(uint64_t));
-    if (e != hipSuccess) return from_hip(e);
-    e = hipMemcpy(pt.dev, h.data(), h.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      (void)hipFree(pt.dev);
-      return from_hip(e);
-    }
-    it = ctx->pass.emplace(N, pt).first;
-  }
   for (int i = 0; i < 2; ++i) {
-    const uint64_t* base = it->second.dev + (size_t)i * per;
+    const uint64_t* base = pt.dev + (size_t)i * per;
     tw->hi_fwd[i] = base;
     tw->lo_fwd[i] = base + HI;
     tw->hi_inv[i] = base + HI + LO;
     tw->lo_inv[i] = base + 2 * HI + LO;
-    tw->scale[i] = it->second.scale[i];
+    tw->scale[i] = pt.scale[i];
   }
+}
+
+// The tables of a plan's length, if they exist already (no allocation).
+bool find_twiddles(const dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw) {
+  auto it = ctx->pass.find(pl.N);
+  if (it == ctx->pass.end()) return false;
+  set_twiddles(ctx, pl, it->second, tw);
+  return true;
+}
+
+// Builds (once per length) the inter-pass factor tables of a transform of
+// length N = R*C and returns pointers to them.
+int get_twiddles(dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw) {
+  if (find_twiddles(ctx, pl, tw)) return DMUL_OK;
+  const int lb = pass_split_bits(pl.logC, pl.rad3);
+  std::vector<uint64_t> h(pass_words(pl.N, lb));
+  PassTables pt;
+  fill_pass_tables(pl.N, lb, h.data(), pt.scale);
+  hipError_t e = hipMalloc(&pt.dev, h.size() * sizeof(uint64_t));
+  if (e != hipSuccess) return from_hip(e);
+  e = hipMemcpy(pt.dev, h.data(), h.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(pt.dev);
+    return from_hip(e);
+  }
+  auto it = ctx->pass.emplace(pl.N, pt).first;
+  set_twiddles(ctx, pl, it->second, tw);
   return DMUL_OK;
 }
 
@@ -297,8 +329,11 @@ int ensure_status(dmul_ctx* ctx, size_t n) {
   e = hipMalloc(&d, cap * sizeof(int));
   if (e != hipSuccess) return from_hip(e);
   e = hipMemsetAsync(d, 0, cap * sizeof(int), ctx->stream);
-  if (e == hipSuccess && ctx->d_status)   // the single-product word carries over
-    e = hipMemcpyAsync(d, ctx->d_status, sizeof(int), hipMemcpyDeviceToDevice, ctx->stream);
+  // the words in use (the single product's and those of batches not yet
+  // synchronised, whose work is complete after the wait above) carry over
+  if (e == hipSuccess && ctx->d_status)
+    e = hipMemcpyAsync(d, ctx->d_status, ctx->status_used * sizeof(int), hipMemcpyDeviceToDevice,
+                       ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     (void)hipFree(d);
@@ -376,9 +411,22 @@ int spectrum_plan(int device, const dmul_spectrum* sa, size_t na, const dmul_spe
   return DMUL_OK;
 }
 
+static int enqueue_one(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
+                       uint64_t* out, unsigned flags, int* status, uint64_t* residues,
+                       const dmul_spectrum* sa, const dmul_spectrum* sb);
+
 int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
                     uint64_t* out, unsigned flags, int* status, uint64_t* residues,
                     const dmul_spectrum* sa, const dmul_spectrum* sb) {
+  if (ctx->timing) ctx->timing->start(ctx->stream);
+  const int rc = enqueue_one(ctx, a, na, b, nb, out, flags, status, residues, sa, sb);
+  if (!rc && ctx->timing) ctx->timing->done.push_back(ctx->timing->record(ctx->stream));
+  return rc;
+}
+
+static int enqueue_one(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
+                       uint64_t* out, unsigned flags, int* status, uint64_t* residues,
+                       const dmul_spectrum* sa, const dmul_spectrum* sb) {
   if (na == 0 || nb == 0) return from_hip(launch_zero(out, na + nb, ctx->stream));
   PlanDev pl;
   int rc = spectrum_plan(ctx->device, sa, na, sb, nb, flags, &pl);
@@ -406,6 +454,11 @@ int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t*
   w.many = nullptr;
   w.count = 1;
   Shape sh{pl.logR, pl.logC, pl.rad3, d.square ? 0 : 1, row_iters_for(ctx, pl), d.nblk};
+  if (ctx->poison) {
+    hipError_t e = launch_fill32(ctx->ws, 2 * workspace_words(pl), kPoison, ctx->stream);
+    if (e == hipSuccess) e = launch_fill32(ctx->rec_sync, d.nblk + 1, kPoison, ctx->stream);
+    if (e != hipSuccess) return from_hip(e);
+  }
   Marks* marks = ctx->prof;
   if (ctx->prof) ctx->prof->begin(ctx->stream);
   if (!residues && !sa && !sb && small_fits(pl, 1))
@@ -532,6 +585,7 @@ int dmul_ctx_create(dmul_ctx** out, int device, size_t budget) {
   if (!c) return DMUL_ENOMEM;
   c->device = device;
   c->budget = budget;
+  if (const char* pv = getenv("DMUL_POISON")) c->poison = pv[0] && strcmp(pv, "0") != 0;
   c->h_div = dt;
   load_tuning(&c->tune);
   for (int i = 0; i < 2; ++i) {
@@ -609,7 +663,9 @@ int dmul_ctx_destroy(dmul_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   delete c->batch;
   delete c->prof;
-  for (auto& kv : c->pass) (void)hipFree(kv.second.dev);
+  delete c->timing;
+  for (auto& kv : c->pass)
+    if (kv.second.owned) (void)hipFree(kv.second.dev);
   if (c->ws) (void)hipFree(c->ws);
   if (c->d_roots) (void)hipFree(c->d_roots);
   if (c->d_r3) (void)hipFree(c->d_r3);
@@ -653,10 +709,11 @@ int dmul_sync(dmul_ctx* c) {
   std::lock_guard<std::mutex> lk(c->mu);
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e == hipSuccess && c->prof) c->prof->collect();
+  if (e == hipSuccess && c->timing) c->timing->collect();
   int rc = c->pending;
   c->pending = DMUL_OK;
   if (e != hipSuccess) rc = from_hip(e);
-  const size_t n = 1 + c->batch_count;
+  const size_t n = c->status_used;
   std::vector<int> st(n, 0);
   e = hipMemcpy(st.data(), c->d_status, n * sizeof(int), hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemset(c->d_status, 0, n * sizeof(int));
@@ -664,12 +721,12 @@ int dmul_sync(dmul_ctx* c) {
   // status bit 1: a limb >= 10^19
   auto code = [](int w) { return (w & 1) ? DMUL_EDIGIT : DMUL_OK; };
   if (st[0] && rc == DMUL_OK) rc = code(st[0]);
-  if (c->batch_status) {
-    for (size_t i = 0; i < c->batch_count; ++i)
-      if (st[1 + i] && c->batch_status[i] == DMUL_OK) c->batch_status[i] = code(st[1 + i]);
+  for (const auto& pb : c->batches) {
+    for (size_t i = 0; i < pb.count; ++i)
+      if (st[pb.off + i] && pb.host[i] == DMUL_OK) pb.host[i] = code(st[pb.off + i]);
   }
-  c->batch_status = nullptr;
-  c->batch_count = 0;
+  c->batches.clear();
+  c->status_used = 1;
   return rc;
 }
 
@@ -772,6 +829,29 @@ int dmul_ctx_profile_events(dmul_ctx* c, int32_t* phases, double* end_ms, int n)
   return m;
 }
 
+int dmul_ctx_timing(dmul_ctx* c, int enable) {
+  if (!c) return DMUL_EINVAL;
+  DeviceGuard dg(c->device);
+  std::lock_guard<std::mutex> lk(c->mu);
+  (void)hipStreamSynchronize(c->stream);
+  delete c->timing;
+  c->timing = nullptr;
+  if (enable) {
+    c->timing = new (std::nothrow) Timing();
+    if (!c->timing) return DMUL_ENOMEM;
+  }
+  return DMUL_OK;
+}
+
+long dmul_ctx_timing_read(dmul_ctx* c, double* ms, size_t n) {
+  if (!c || (n && !ms)) return DMUL_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!c->timing) return 0;
+  const std::vector<double>& t = c->timing->last;
+  for (size_t i = 0; i < n && i < t.size(); ++i) ms[i] = t[i];
+  return (long)t.size();
+}
+
 const char* dmul_phase_name(int phase) {
   static const char* names[kNumPhases] = {"fwd_cols", "fwd_rows", "inv_rows", "inv_cols",
                                           "rec_crt", "rec_apply", "whole", "rows"};
@@ -796,16 +876,22 @@ int dmul_batch_ex(dmul_ctx* c, size_t count, const uint64_t* const* a, const siz
   DeviceGuard dg(c->device);
   if (!dg.ok()) return DMUL_EDEVICE;
   std::lock_guard<std::mutex> lk(c->mu);
-  int rc = ensure_status(c, 1 + count);
-  if (rc) return rc;
-  for (size_t i = 0; i < count; ++i) status[i] = DMUL_OK;
   if (!c->batch) {
     c->batch = new (std::nothrow) BatchEngine();
     if (!c->batch) return DMUL_ENOMEM;
   }
-  rc = c->batch->run(c, count, a, na, sa, b, nb, sb, out, status, flags, c->d_status + 1);
-  c->batch_status = status;
-  c->batch_count = count;
+  // this batch's status words follow those of the batches not yet synchronised
+  const size_t off = c->status_used;
+  int rc = ensure_status(c, off + count);
+  if (rc) return rc;
+  try {
+    c->batches.push_back({status, off, count});
+  } catch (const std::bad_alloc&) {
+    return DMUL_ENOMEM;
+  }
+  c->status_used = off + count;
+  for (size_t i = 0; i < count; ++i) status[i] = DMUL_OK;
+  rc = c->batch->run(c, count, a, na, sa, b, nb, sb, out, status, flags, c->d_status + off);
   if (rc == DMUL_EDEVICE && c->pending == DMUL_OK) c->pending = rc;
   return rc;
 }

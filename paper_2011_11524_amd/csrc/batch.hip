@@ -117,7 +117,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
   // kernel sequence without planning again.  Captured graphs are dropped
   // whenever the engine's buffers or the tuning change.  The legacy null
   // stream cannot be captured, so graphs need a created stream.
-  bool graph = (flags & DMUL_FLAG_GRAPH) && ctx->stream != nullptr && !ctx->prof;
+  bool graph = (flags & DMUL_FLAG_GRAPH) && ctx->stream != nullptr && !ctx->prof && !ctx->timing;
   uint64_t sig = 1469598103934665603ULL;
   std::vector<uint64_t> key;
   if (graph) {
@@ -153,6 +153,14 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       return from_hip(hipGraphLaunch(it->second.exec, ctx->stream));
     }
   }
+  // completion timing: every product starts at the batch's start event and
+  // gets its size class's completion event below
+  size_t tbase = 0;
+  if (ctx->timing) {
+    ctx->timing->start(ctx->stream);
+    tbase = ctx->timing->done.size();
+    ctx->timing->done.resize(tbase + count, 0);
+  }
   // plan, and group the products by transform length (and whether cached
   // spectra stand in for operands: those never take the one-workgroup kernel)
   std::vector<PlanDev> plans(count);
@@ -186,11 +194,11 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
   // the staging buffer may still feed the previous batch's copy
   if (hipEventSynchronize(copied_) != hipSuccess) return DMUL_EDEVICE;
   size_t wofs = 0, sofs = 0, di = 0;
-  struct Cls { PlanDev p0; int spectra; size_t first, n; Shape sh; };
+  struct Cls { PlanDev p0; int spectra; size_t first, n; Shape sh; const std::vector<uint32_t>* idx; };
   std::vector<Cls> cls;
   for (auto& kv : classes) {
     const PlanDev& p0 = plans[kv.second[0]];
-    Cls c{p0, kv.first.second, di, kv.second.size(), {}};
+    Cls c{p0, kv.first.second, di, kv.second.size(), {}, &kv.second};
     c.sh.logR = p0.logR;
     c.sh.logC = p0.logC;
     c.sh.rad3 = p0.rad3;
@@ -240,6 +248,16 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
     if (graph) (void)hipFree(descs);
     return from_hip(e);
   }
+  // DMUL_POISON: every workspace and map word of the batch starts as
+  // garbage (filled here, before any capture begins)
+  if (ctx->poison) {
+    e = launch_fill32(ws_, 2 * ws_words, kPoison, ctx->stream);
+    if (e == hipSuccess) e = launch_fill32(sync_, sync_words, kPoison, ctx->stream);
+    if (e != hipSuccess) {
+      if (graph) (void)hipFree(descs);
+      return from_hip(e);
+    }
+  }
   // side streams and events exist before any capture begins
   const bool fork = !ctx->prof && cls.size() > 1 && ensure_side_streams() == DMUL_OK;
   if (graph) {
@@ -284,6 +302,10 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       if (e == hipSuccess) e = launch_recover(w, c.sh, ctx->cs, ctx->d_div, &ctx->h_div, st, marks);
     }
     if (e != hipSuccess) break;
+    if (ctx->timing) {
+      const size_t ev = ctx->timing->record(st);
+      for (uint32_t i : *c.idx) ctx->timing->done[tbase + i] = ev;
+    }
   }
   // join: the context stream continues only after every side stream's classes
   for (int i = 0; i < nside; ++i) {

@@ -231,6 +231,11 @@ __global__ void k_zero(uint64_t* __restrict__ out, size_t n) {
     out[i] = 0;
 }
 
+__global__ void k_fill32(uint32_t* __restrict__ out, size_t n, uint32_t v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = v;
+}
+
 constexpr int kRecPT = 4;
 constexpr int kRecBlock = kRecThreads * kRecPT;    // positions per workgroup
 
@@ -285,6 +290,13 @@ hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, cons
   else
     hipLaunchKernelGGL((k_rec_apply<kRecPT, false>), dim3(g, 1, w.count), dim3(kRecThreads), 0, st, w, rt, dt);
   if (marks) marks->mark(kRecApply, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill32(void* out, size_t n, uint32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_fill32, dim3(blocks), dim3(256), 0, st, (uint32_t*)out, n, v);
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ struct TuneTable {
 struct PassTables {
   uint64_t scale[2] = {};     // R^2 N^-1 mod p per prime
   uint64_t* dev = nullptr;   // per prime: hi_fwd[N >> lb] lo_fwd[2^lb] hi_inv[N >> lb] lo_inv[2^lb]
+  bool owned = true;         // dev is its own allocation (not part of the prebuilt block)
 };
 
 // Per-kernel event timing (dmul_ctx_profile): an event before the first
@@ -74,6 +75,44 @@ struct Profiler : Marks {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
 };
+
+// Completion timing (dmul_ctx_timing): one event when the first work after a
+// dmul_sync is enqueued, and one event per completed unit of work -- after
+// each dmul_ex product, and after each size class of a batch on the stream
+// that class runs on -- so the per-product completion times describe the
+// same concurrent schedule that runs without timing.
+struct Timing {
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<size_t> done;       // per product since the last sync: its completion event
+  std::vector<double> last;       // ms after the start event, work completed by the last sync
+
+  size_t record(hipStream_t st) {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return SIZE_MAX;
+      pool.push_back(e);
+    }
+    if (hipEventRecord(pool[used], st) != hipSuccess) return SIZE_MAX;
+    return used++;
+  }
+  // the start event, recorded before the first work since the last sync
+  void start(hipStream_t st) {
+    if (used == 0) (void)record(st);
+  }
+  void collect() {
+    last.assign(done.size(), -1.0);
+    for (size_t i = 0; i < done.size(); ++i) {
+      float ms = 0.f;
+      if (done[i] < used && hipEventElapsedTime(&ms, pool[0], pool[done[i]]) == hipSuccess) last[i] = ms;
+    }
+    done.clear();
+    used = 0;
+  }
+  ~Timing() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
 }  // namespace dmi
 
 using dmi::Consts;
@@ -91,16 +130,21 @@ struct dmul_ctx {
   std::map<uint64_t, dmi::PassTables> pass; // by N
   uint64_t* ws = nullptr;
   size_t ws_words = 0;
-  int* d_status = nullptr;              // [0]: dmul_ex; [1 + i]: batch product i
+  int* d_status = nullptr;              // [0]: dmul_ex; then one region per batch since dmul_sync
   size_t status_cap = 0;
+  size_t status_used = 1;               // words in use: [0] and every pending batch's region
   int pending = DMUL_OK;
-  int32_t* batch_status = nullptr;      // host array to fill at dmul_sync
-  size_t batch_count = 0;
+  // batches enqueued since the last dmul_sync: each reports to its own words
+  // d_status[off .. off + count), copied into its host array at dmul_sync
+  struct PendingBatch { int32_t* host; size_t off, count; };
+  std::vector<PendingBatch> batches;
   dmi::BatchEngine* batch = nullptr;
   dmi::Profiler* prof = nullptr;
+  dmi::Timing* timing = nullptr;
   uint32_t* rec_sync = nullptr;         // recovery: one carry map per block
   size_t rec_sync_cap = 0;
   dmi::TuneTable tune;                  // per transform length launch parameters
+  bool poison = false;                  // DMUL_POISON: fill scratch with 0xff before every product
   std::mutex mu;
 };
 
@@ -148,6 +192,8 @@ class DeviceGuard {
 int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl);
 size_t workspace_words(const PlanDev& pl);
 int get_twiddles(dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw);
+bool find_twiddles(const dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw);
+int layout_logR(int e, int rad3);
 int ensure_workspace(dmul_ctx* ctx, size_t words);
 int ensure_rec_sync(dmul_ctx* ctx, size_t words);
 int row_iters_for(const dmul_ctx* ctx, const PlanDev& pl);

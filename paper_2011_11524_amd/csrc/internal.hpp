@@ -152,5 +152,9 @@ hipError_t allow_lds(const void* kernel, size_t lds_bytes);
 size_t recover_blocks(const PlanDev& pl);
 size_t recover_scratch_words(const PlanDev& pl);
 hipError_t launch_zero(uint64_t* out, size_t n, hipStream_t stream);
+// n 32-bit words of v (the scratch poisoning of contexts made with
+// DMUL_POISON set: workspaces start as garbage, never as the last product's).
+hipError_t launch_fill32(void* out, size_t n, uint32_t v, hipStream_t stream);
+constexpr uint32_t kPoison = 0xffffffffu;
 
 }  // namespace dmi

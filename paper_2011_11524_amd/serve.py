@@ -16,6 +16,15 @@ its batch complete (a HIP event on the engine's stream).  The loop is
 argument marshalling and bookkeeping only; every product runs in the
 library's kernels.
 
+Failures stay with their request.  A request whose footprint alone exceeds
+the engine budget is refused at admission (status DMUL_ENOMEM).  Each
+engine's library context enforces the same budget.  A batch the library
+refuses as a whole (DMUL_ENOMEM from the workspace budget or an allocation,
+or an argument error) is split, and each of its requests is run again alone;
+a request that fails alone, or whose own product fails (DMUL_EDIGIT for a
+limb >= 10^19), is reported with its status and the loop goes on.  Only a
+device error (DMUL_EDEVICE) ends the loop.
+
 Transforms can stay resident too: with a spectrum cache, an operand that
 comes back (the same pool slice, in a product of the same plan k and N)
 gets its forward transforms cached as a dmul spectrum, and later products
@@ -28,12 +37,13 @@ from __future__ import annotations
 import ctypes
 import gc
 import time
-from collections import OrderedDict
+from collections import OrderedDict, deque
 from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Context, DmulError, lib, plan, spectrum_bytes, torch, workspace_bytes
+from . import (DMUL_EDEVICE, DMUL_ENOMEM, Context, DmulError, lib, plan, spectrum_bytes, torch,
+               workspace_bytes)
 
 
 @dataclass
@@ -44,6 +54,11 @@ class Request:
     b_off: int
     nb: int
     arrival: float      # seconds after the start of the run
+    da: int = 0         # requested decimal digits of a and b (0: 19 per limb)
+    db: int = 0
+
+    def digits(self) -> int:
+        return (self.da or 19 * self.na) + (self.db or 19 * self.nb)
 
 
 @dataclass
@@ -55,8 +70,11 @@ class ServeStats:
     latencies_s: list = field(default_factory=list)
     max_inflight_bytes: int = 0
     max_overlap: int = 0        # largest number of batches in flight at once
+    max_batch_bytes: int = 0    # largest footprint of one batch (at most the engine budget)
     spectrum_hits: int = 0      # operands taken from cached transforms
     spectra_made: int = 0
+    failed: dict = field(default_factory=dict)   # rid -> status of requests that failed
+    retried: int = 0            # requests run again alone after their batch was refused
 
     def summary(self) -> dict:
         lat = np.asarray(self.latencies_s, dtype=float) * 1e3
@@ -70,18 +88,22 @@ class ServeStats:
             "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
             "mean_batch": self.completed / self.batches if self.batches else 0,
             "max_inflight_bytes": self.max_inflight_bytes,
+            "max_batch_bytes": self.max_batch_bytes,
             "max_batches_in_flight": self.max_overlap,
             "spectrum_hits": self.spectrum_hits,
             "spectra_made": self.spectra_made,
+            "failed": len(self.failed),
+            "retried_alone": self.retried,
         }
 
 
 class _Engine:
     """One dmul context with its own stream; at most one batch in flight."""
 
-    def __init__(self, device: int, budget: int):
+    def __init__(self, device: int, budget: int, ctx_budget: int):
         self.stream = torch.cuda.Stream(device=device)
-        self.ctx = Context(device, budget_bytes=0, stream=self.stream)
+        # the library enforces the workspace budget itself
+        self.ctx = Context(device, budget_bytes=ctx_budget, stream=self.stream)
         self.budget = budget
         self.busy = None            # (event, requests, out buffer, bytes) of the batch in flight
 
@@ -101,13 +123,17 @@ class Server:
     spectrum_min_len: the shortest transform length worth caching: making a
         spectrum costs host work and two launches of its own, which pays off
         only where a forward transform is long.
+    ctx_budget_bytes: the workspace budget of each engine's library context
+        (default: budget_bytes).
     """
 
     def __init__(self, pool, device: int = 0, engines: int = 2, budget_bytes: int = 8 << 30,
-                 max_batch: int = 1024, spectrum_cache_bytes: int = 0, spectrum_min_len: int = 1 << 19):
+                 max_batch: int = 1024, spectrum_cache_bytes: int = 0, spectrum_min_len: int = 1 << 19,
+                 ctx_budget_bytes: int | None = None):
         self.pool = pool
         self.device = device
-        self.engines = [_Engine(device, budget_bytes) for _ in range(max(1, engines))]
+        cb = budget_bytes if ctx_budget_bytes is None else ctx_budget_bytes
+        self.engines = [_Engine(device, budget_bytes, cb) for _ in range(max(1, engines))]
         self.max_batch = max_batch
         self._base = pool.data_ptr()
         self.spec_cap = int(spectrum_cache_bytes)
@@ -199,32 +225,56 @@ class Server:
             rc = eng.ctx._lib.dmul_batch_ex(eng.ctx._h, n, A, NA, SA, B, NB, SB, O, st, 0)
         else:
             rc = eng.ctx._lib.dmul_batch(eng.ctx._h, n, A, NA, B, NB, O, st, 0)
-        if rc:
+        if rc == DMUL_EDEVICE:
             raise DmulError(rc, "dmul_batch")
+        if rc:
+            # refused as a whole (nothing enqueued): every request is run
+            # again alone, or fails with this status if it already was alone
+            self._refused(reqs, rc)
+            return False
         ev = torch.cuda.Event()
         ev.record(eng.stream)
         nbytes = sum(self.footprint(r.na, r.nb) for r in reqs)
         eng.busy = (ev, reqs, out if keep_outputs else None, nbytes, (A, B, O, NA, NB, st, SA, SB, used))
+        return True
+
+    def _refused(self, reqs: list, rc: int):
+        """Requests whose batch the library refused (rc): alone again, or
+        failed if they were alone."""
+        if len(reqs) == 1:
+            self._fail(reqs[0], rc)
+            return
+        for r in reversed(reqs):
+            self._alone.appendleft(r)
+        self._stats.retried += len(reqs)
+
+    def _fail(self, r: Request, rc: int):
+        self._stats.failed[r.rid] = int(rc)
+        self._stats.completed += 1
 
     def _retire(self, eng: _Engine, t0: float, stats: ServeStats, results: dict | None):
         ev, reqs, out, nbytes, keep = eng.busy
+        eng.busy = None
         now = time.perf_counter() - t0
         rc = eng.ctx._lib.dmul_sync(eng.ctx._h)      # stream already idle: returns at once
         if rc:
-            raise DmulError(rc, "dmul_sync")
+            raise DmulError(rc, "dmul_sync")      # a device error: nothing is trustworthy
         st = keep[5]
+        ofs, refused = 0, []
         for i, r in enumerate(reqs):
-            if st[i] != 0:
-                raise DmulError(st[i], f"request {r.rid}")
-            stats.latencies_s.append(now - r.arrival)
-            stats.digits += 19 * (r.na + r.nb)
-        stats.completed += len(reqs)
-        if results is not None and out is not None:
-            ofs = 0
-            for r in reqs:
-                results[r.rid] = out[ofs: ofs + r.na + r.nb]
-                ofs += r.na + r.nb
-        eng.busy = None
+            if st[i] == DMUL_ENOMEM and len(reqs) > 1:
+                refused.append(r)                 # the batch's workspace: run it alone
+            elif st[i] != 0:
+                self._fail(r, st[i])
+            else:
+                stats.latencies_s.append(now - r.arrival)
+                stats.digits += r.digits()
+                stats.completed += 1
+                if results is not None and out is not None:
+                    results[r.rid] = out[ofs: ofs + r.na + r.nb]
+            ofs += r.na + r.nb
+        if refused:
+            self._refused(refused, DMUL_ENOMEM)
 
     def run(self, reqs: list, keep_outputs: bool = False, realtime: bool = True) -> tuple[ServeStats, dict]:
         """Serve `reqs` (sorted by arrival).  With realtime, a request is
@@ -246,6 +296,7 @@ class Server:
     def _run(self, reqs: list, stats: ServeStats, keep_outputs: bool, realtime: bool):
         results = {} if keep_outputs else None
         nxt = 0                      # next request not yet admitted
+        self._alone = deque()        # requests to run again, each alone
         t0 = time.perf_counter()
         while stats.completed < len(reqs):
             now = time.perf_counter() - t0
@@ -255,29 +306,41 @@ class Server:
             inflight = sum(1 for e in self.engines if e.busy is not None)
             launched = False
             for eng in self.engines:
-                if eng.busy is not None or nxt >= len(reqs):
+                if eng.busy is not None:
                     continue
-                if realtime and reqs[nxt].arrival > now:
-                    break
-                batch, used = [], 0
-                while (nxt < len(reqs) and len(batch) < self.max_batch
-                       and (not realtime or reqs[nxt].arrival <= now)):
-                    r = reqs[nxt]
-                    fp = self.footprint(r.na, r.nb)
-                    if batch and used + fp > eng.budget:
+                if self._alone:
+                    batch = [self._alone.popleft()]
+                else:
+                    if nxt >= len(reqs) or (realtime and reqs[nxt].arrival > now):
                         break
-                    batch.append(r)
-                    used += fp
-                    nxt += 1
-                self._launch(eng, batch, keep_outputs)
+                    batch, used = [], 0
+                    while (nxt < len(reqs) and len(batch) < self.max_batch
+                           and (not realtime or reqs[nxt].arrival <= now)):
+                        r = reqs[nxt]
+                        fp = self.footprint(r.na, r.nb)
+                        if fp > eng.budget:           # can never fit: refused, not admitted
+                            self._fail(r, DMUL_ENOMEM)
+                            nxt += 1
+                            continue
+                        if used + fp > eng.budget:
+                            break
+                        batch.append(r)
+                        used += fp
+                        nxt += 1
+                    if not batch:
+                        continue
+                if not self._launch(eng, batch, keep_outputs):
+                    continue
                 stats.batches += 1
                 inflight += 1
                 stats.max_overlap = max(stats.max_overlap, inflight)
                 stats.max_inflight_bytes = max(
                     stats.max_inflight_bytes, sum(e.busy[3] for e in self.engines if e.busy is not None))
+                stats.max_batch_bytes = max(stats.max_batch_bytes, eng.busy[3])
                 launched = True
             if not launched:
-                if all(e.busy is None for e in self.engines) and nxt < len(reqs) and realtime:
+                if (all(e.busy is None for e in self.engines) and nxt < len(reqs) and realtime
+                        and not self._alone):
                     wait = reqs[nxt].arrival - (time.perf_counter() - t0)
                     if wait > 0:
                         time.sleep(min(wait, 1e-3))
@@ -297,5 +360,5 @@ def make_requests(lengths_a, lengths_b, arrivals, pool_limbs: int, seed: int = 5
         nb = max(1, (int(db) + 18) // 19)
         ao = int(rng.integers(0, pool_limbs - na + 1))
         bo = int(rng.integers(0, pool_limbs - nb + 1))
-        reqs.append(Request(i, ao, na, bo, nb, float(t)))
+        reqs.append(Request(i, ao, na, bo, nb, float(t), max(1, int(da)), max(1, int(db))))
     return reqs

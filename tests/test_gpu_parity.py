@@ -239,16 +239,17 @@ def _mod_pm(limbs):
 
 
 @pytest.mark.parametrize("e", [20, 22, 23])
-def test_radix3_long_rows_properties(dm, ctx, e):
-    """The longest layouts of 3*2^e (2^10..2^12 rows of 3*2^10..3*2^11 points), too
-    long for the oracle in a test: the product's residues modulo 10^19 - 1
-    and 10^19 + 1 (casting out, exact at any size) and equality with the
-    power-of-two path."""
+def test_radix3_long_rows_vs_oracle(dm, ctx, e):
+    """The longest layouts of 3*2^e (2^10..2^12 rows of 3*2^10..3*2^11 points,
+    the column kernels of 2^11 and 2^12 points) limb by limb against the
+    oracle (whose power-of-two transform of up to 2^25 points takes tens of
+    seconds on the host), plus the product's residues modulo 10^19 - 1 and
+    10^19 + 1 and equality with the power-of-two path."""
     N = 3 << e
     na, nb = _sizes_with_length(dm, N, 100 + e)
     pl = dm.plan(na, nb)
     assert pl.factor == 3 and pl.log2_n == e
-    _note(f"radix-3 N=3*2^{e} ({pl.log2_rows}x3*2^{pl.log2_cols}) {na}x{nb} properties")
+    _note(f"radix-3 N=3*2^{e} ({pl.log2_rows}x3*2^{pl.log2_cols}) {na}x{nb} vs oracle")
     rng = np.random.default_rng(8000 + e)
     a = rng.integers(0, 10 ** 19, size=na, dtype=np.uint64)
     b = rng.integers(0, 10 ** 19, size=nb, dtype=np.uint64)
@@ -257,8 +258,23 @@ def test_radix3_long_rows_properties(dm, ctx, e):
     (a1, a2), (b1, b2), (z1, z2) = _mod_pm(a), _mod_pm(b), _mod_pm(got)
     assert z1 == a1 * b1 % (10 ** 19 - 1)
     assert z2 == a2 * b2 % (10 ** 19 + 1)
-    if pl.N < (1 << 26):
-        np.testing.assert_array_equal(_gpu_mul(dm, ctx, a, b, pow2=True), got)
+    np.testing.assert_array_equal(_gpu_mul(dm, ctx, a, b, pow2=True), got)
+    np.testing.assert_array_equal(got, oracle.mul_ntt(a, b))
+
+
+def test_power_of_two_2_24_vs_oracle(dm, ctx):
+    """N = 2^24 (4096 x 4096, the 2^12-point column and row kernels), chosen
+    by the planner because 3*2^22 is too short: limb by limb against the
+    oracle."""
+    na, nb = 7_000_000, 5_600_000
+    pl = dm.plan(na, nb)
+    assert (pl.N, pl.factor, pl.log2_rows, pl.log2_cols) == (1 << 24, 1, 12, 12)
+    _note(f"N=2^24 {na}x{nb} limbs, k={pl.k} vs oracle")
+    rng = np.random.default_rng(2424)
+    a = rng.integers(0, 10 ** 19, size=na, dtype=np.uint64)
+    b = rng.integers(0, 10 ** 19, size=nb, dtype=np.uint64)
+    got = _gpu_mul(dm, ctx, a, b)
+    np.testing.assert_array_equal(got, oracle.mul_ntt(a, b))
 
 
 @pytest.mark.parametrize("n", [1, 2, 50, 81, 777, 5264])
@@ -418,6 +434,34 @@ def test_batch_reports_per_product_status(dm, ctx):
     np.testing.assert_array_equal(dm.to_host(outs[2]), oracle.mul_ntt([1, 2, 3], [1, 2, 3]))
 
 
+def test_two_batches_before_one_sync(dm, ctx):
+    """Two batches enqueued before one sync report to their own status
+    arrays: the bad limb of the first batch's product 1 is reported there,
+    and no product of the second batch is blamed for it."""
+    import torch
+    _note("two batches, one sync, bad limb in the first")
+    rng = random.Random(4343)
+    good = [(_rand_limbs(rng, n), _rand_limbs(rng, m)) for n, m in ((3, 4), (90, 70), (600, 500))]
+    dev = [(dm.to_device(a), dm.to_device(b)) for a, b in good]
+    bad = dm.to_device(np.array([10 ** 19 + 5, 1], np.uint64))
+    first = [dev[0], (bad, dev[1][1]), dev[2]]
+    second = [dev[2], dev[1], dev[0]]
+    outs1 = [torch.empty(x.numel() + y.numel(), dtype=torch.uint64, device="cuda") for x, y in first]
+    outs2 = [torch.empty(x.numel() + y.numel(), dtype=torch.uint64, device="cuda") for x, y in second]
+    st1 = ctx.batch_async(first, outs1)
+    st2 = ctx.batch_async(second, outs2)
+    ctx.sync()
+    assert list(st1) == [0, dm.DMUL_EDIGIT, 0]
+    assert list(st2) == [0, 0, 0]
+    for i in (0, 2):
+        np.testing.assert_array_equal(dm.to_host(outs1[i]), oracle.mul_ntt(*good[i]))
+    for (a, b), o in zip([good[2], good[1], good[0]], outs2):
+        np.testing.assert_array_equal(dm.to_host(o), oracle.mul_ntt(a, b))
+    # the words are cleared by the sync: a clean batch afterwards reports OK
+    _, st3 = ctx.batch(second)
+    assert st3 == [0, 0, 0]
+
+
 def test_repeatable(dm, ctx):
     _note("determinism")
     a = synth.random_operand(300_000, 7)
@@ -536,7 +580,9 @@ def test_context_budget_enomem(dm):
 def test_largest_power_of_two_length(dm, ctx):
     """The longest transform, N = 2^26 (8192 x 8192, two 3*10^8-digit
     operands at k = 15): the product's residues modulo 10^19 - 1 and
-    10^19 + 1, exact at any size, and the digit range."""
+    10^19 + 1, exact at any size, and the digit range.  Not against the
+    oracle: its transform of 2^26 points takes more than a minute per prime
+    pass on the host, beyond a test's time limit."""
     na = nb = 15_800_000
     pl = dm.plan(na, nb)
     assert (pl.N, pl.factor, pl.log2_rows, pl.log2_cols) == (1 << 26, 1, 13, 13)

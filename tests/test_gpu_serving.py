@@ -74,10 +74,97 @@ def test_admission_respects_budget(env):
         stats, _ = srv.run(reqs, realtime=False)
     finally:
         srv.close()
-    assert stats.completed == n
-    biggest = max(serve.Server.footprint(r.na, r.nb) for r in reqs)
-    assert stats.max_inflight_bytes <= 2 * max(budget, biggest)
+    assert stats.completed == n and not stats.failed
+    assert all(serve.Server.footprint(r.na, r.nb) <= budget for r in reqs)
+    # every batch fits one engine's budget; two engines hold at most two batches
+    assert 0 < stats.max_batch_bytes <= budget
+    assert stats.max_inflight_bytes <= 2 * budget
     assert stats.batches > 2
+
+
+def _alone(dm, torch, pool, r):
+    a = pool[r.a_off: r.a_off + r.na].contiguous()
+    b = pool[r.b_off: r.b_off + r.nb].contiguous()
+    return dm.mul(a, b)
+
+
+def test_oversized_request_refused_alone(env):
+    """A request whose footprint alone exceeds the budget is refused with
+    DMUL_ENOMEM; the requests around it are served and equal their products
+    alone."""
+    dm, serve, torch, pool_h, pool = env
+    _note("serving: oversized request")
+    budget = 1 << 20
+    reqs = [serve.Request(0, 10, 300, 900, 250, 0.0),
+            serve.Request(1, 5000, 20000, 100, 20000, 0.0),     # ~2.5 MB workspace
+            serve.Request(2, 77, 40, 3000, 600, 0.0)]
+    assert serve.Server.footprint(20000, 20000) > budget
+    srv = serve.Server(pool, engines=2, budget_bytes=budget, max_batch=16)
+    try:
+        stats, res = srv.run(reqs, keep_outputs=True, realtime=False)
+    finally:
+        srv.close()
+    assert stats.failed == {1: dm.DMUL_ENOMEM}
+    assert sorted(res) == [0, 2] and stats.completed == 3
+    for r in (reqs[0], reqs[2]):
+        assert torch.equal(res[r.rid], _alone(dm, torch, pool, r))
+
+
+def test_bad_limb_request_isolated(env):
+    """A request with a limb >= 10^19 fails with DMUL_EDIGIT; the rest of its
+    batch and the loop go on."""
+    dm, serve, torch, pool_h, pool = env
+    _note("serving: bad limb in one request")
+    bad_h = pool_h.copy()
+    bad_h[20000] = np.uint64(10 ** 19 + 3)
+    bad = dm.to_device(bad_h)
+    reqs = [serve.Request(i, 100 * i, 50 + 7 * i, 30000 + 11 * i, 90, 0.0) for i in range(12)]
+    reqs[5] = serve.Request(5, 19990, 40, 100, 30, 0.0)           # reads limb 20000
+    srv = serve.Server(bad, engines=2, budget_bytes=64 << 20, max_batch=64)
+    try:
+        stats, res = srv.run(reqs, keep_outputs=True, realtime=False)
+    finally:
+        srv.close()
+    assert stats.failed == {5: dm.DMUL_EDIGIT}
+    assert stats.completed == 12 and len(res) == 11
+    for r in reqs:
+        if r.rid != 5:
+            assert torch.equal(res[r.rid], _alone(dm, torch, bad, r))
+
+
+def test_refused_batch_retried_alone(env):
+    """When the library refuses a batch's workspace (its context budget
+    holds one product of these, the engine admits several), every request of
+    the batch is run again alone and served correctly."""
+    dm, serve, torch, pool_h, pool = env
+    _note("serving: batch refused by the library budget, requests retried alone")
+    n, na, nb = 10, 700, 650
+    ws = dm.workspace_bytes(na, nb)
+    reqs = [serve.Request(i, 1000 * i, na, 40000 - 500 * i, nb, 0.0) for i in range(n)]
+    srv = serve.Server(pool, engines=2, budget_bytes=8 * ws, max_batch=64, ctx_budget_bytes=ws)
+    try:
+        stats, res = srv.run(reqs, keep_outputs=True, realtime=False)
+    finally:
+        srv.close()
+    assert not stats.failed and stats.completed == n
+    assert stats.retried >= 2
+    for r in reqs:
+        assert torch.equal(res[r.rid], _alone(dm, torch, pool, r))
+    r = reqs[3]
+    want = oracle.mul_ntt(pool_h[r.a_off: r.a_off + r.na], pool_h[r.b_off: r.b_off + r.nb])
+    np.testing.assert_array_equal(res[r.rid].cpu().numpy(), want)
+
+
+def test_digits_counted_as_requested(env):
+    dm, serve, torch, pool_h, pool = env
+    _note("serving: digit accounting")
+    reqs = serve.make_requests([100, 1000], [20, 57], np.zeros(2), len(pool_h), seed=3)
+    srv = serve.Server(pool, engines=1, budget_bytes=64 << 20)
+    try:
+        stats, _ = srv.run(reqs, realtime=False)
+    finally:
+        srv.close()
+    assert stats.digits == 100 + 20 + 1000 + 57
 
 
 def test_spectrum_cache_reuses_hot_operands(env):
