@@ -123,6 +123,24 @@ int dmul_ctx_set_stream(dmul_ctx* ctx, void* hip_stream);
  * reported by the next dmul_sync.  `flags`: 0 or DMUL_FLAG_FORCE_K(k). */
 int dmul_ex(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
             uint64_t* out, unsigned flags);
+/* dmul_ex_noalloc: dmul_ex for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and error reporting as dmul_ex, but
+ * the call allocates nothing: the product's scratch (its 4N-word workspace
+ * and its carry-map words) is a static device array of the library
+ * (64 MiB + 16 KiB on every device the library runs on, held until the
+ * process ends), and the tables of every transform length up to 2^21 are
+ * built when the context is created.  Returns DMUL_ENOMEM for a product
+ * whose transform length N (dmul_plan) exceeds 2^21 (at most about
+ * 1.5 * 10^7 digits in all).  Every call on one device shares that
+ * device's array and leaves its contents behind: calls that overlap on one
+ * device -- on two streams or two contexts of that device, without a
+ * dmul_sync or stream ordering between them -- race and give wrong
+ * products.  Profiling and completion timing do not record these
+ * products. */
+int dmul_ex_noalloc(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
+                    uint64_t* out, unsigned flags);
+
 /* Waits for everything enqueued on the context; returns DMUL_OK, or the
  * first error seen on the device since the last dmul_sync (DMUL_EDIGIT /
  * DMUL_EDEVICE).  */

@@ -37,7 +37,7 @@ EXPORTS = ("dmul", "dmul_ctx_create", "dmul_ctx_destroy", "dmul_ctx_set_stream",
            "dmul_host", "dmul_primes", "dmul_debug_residues", "dmul_version", "dmul_ctx_profile",
            "dmul_ctx_profile_read", "dmul_phase_name", "dmul_ctx_profile_events", "dmul_ctx_tune",
            "dmul_spectrum_create", "dmul_spectrum_destroy", "dmul_spectrum_bytes", "dmul_ex_spectrum",
-           "dmul_batch_ex", "dmul_ctx_timing", "dmul_ctx_timing_read")
+           "dmul_batch_ex", "dmul_ctx_timing", "dmul_ctx_timing_read", "dmul_ex_noalloc")
 
 
 class DmulError(RuntimeError):
@@ -90,6 +90,7 @@ def lib():
     L.dmul_ctx_set_stream.argtypes = [vp, vp]
     L.dmul_ex.argtypes = [vp, vp, sz, vp, sz, vp, ctypes.c_uint]
     L.dmul_sync.argtypes = [vp]
+    L.dmul_ex_noalloc.argtypes = [vp, vp, sz, vp, sz, vp, ctypes.c_uint]
     L.dmul_batch.argtypes = [vp, sz, ctypes.POINTER(vp), ctypes.POINTER(sz), ctypes.POINTER(vp),
                              ctypes.POINTER(sz), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int32),
                              ctypes.c_uint]
@@ -243,6 +244,20 @@ class Context:
                                ctypes.c_void_p(out.data_ptr()), flags_for(force_k, pow2))
         if rc:
             raise DmulError(rc, "dmul_ex")
+
+    def mul_noalloc_async(self, a, b, out, force_k: int = 0, pow2: bool = False) -> None:
+        """dmul_ex_noalloc: the product in the library's static scratch (no
+        device allocation; transform lengths up to 2^21)."""
+        _check_limbs(a, "a")
+        _check_limbs(b, "b")
+        _check_limbs(out, "out")
+        if out.numel() != a.numel() + b.numel():
+            raise ValueError("out must hold len(a) + len(b) limbs")
+        rc = self._lib.dmul_ex_noalloc(self._h, ctypes.c_void_p(a.data_ptr()), a.numel(),
+                                       ctypes.c_void_p(b.data_ptr()), b.numel(),
+                                       ctypes.c_void_p(out.data_ptr()), flags_for(force_k, pow2))
+        if rc:
+            raise DmulError(rc, "dmul_ex_noalloc")
 
     def sync(self) -> None:
         rc = self._lib.dmul_sync(self._h)

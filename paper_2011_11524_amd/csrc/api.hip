@@ -249,6 +249,41 @@ static void fill_pass_tables(uint64_t N, int lb, uint64_t* h, uint64_t scale[2])
   }
 }
 
+// The tables of every length up to kStaticMaxN, in one allocation made when
+// the context is created (so products of those lengths, dmul_ex_noalloc's
+// included, never allocate tables).
+int prebuild_pass_tables(dmul_ctx* ctx) {
+  struct Len { uint64_t N; int lb; size_t off; };
+  std::vector<Len> lens;
+  size_t total = 0;
+  for (int rad3 = 0; rad3 < 2; ++rad3) {
+    for (int e = rad3 ? kMinLogN3 : 2; e <= kMaxLogN; ++e) {
+      const uint64_t N = (uint64_t)(rad3 ? 3 : 1) << e;
+      const int logR = layout_logR(e, rad3);
+      if (N > kStaticMaxN || (rad3 && logR > kMaxLogR3)) break;
+      const int lb = pass_split_bits(e - logR, rad3);
+      lens.push_back({N, lb, total});
+      total += pass_words(N, lb);
+    }
+  }
+  std::vector<uint64_t> h(total);
+  std::vector<std::pair<uint64_t, PassTables>> ents;
+  for (const Len& l : lens) {
+    PassTables pt;
+    fill_pass_tables(l.N, l.lb, h.data() + l.off, pt.scale);
+    pt.owned = false;
+    ents.push_back({l.N, pt});
+  }
+  hipError_t e = hipMalloc(&ctx->pass_block, total * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMemcpy(ctx->pass_block, h.data(), total * sizeof(uint64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return from_hip(e);
+  for (size_t i = 0; i < lens.size(); ++i) {
+    ents[i].second.dev = ctx->pass_block + lens[i].off;
+    ctx->pass.emplace(ents[i].first, ents[i].second);
+  }
+  return DMUL_OK;
+}
+
 static void set_twiddles(const dmul_ctx* ctx, const PlanDev& pl, const PassTables& pt, TwiddleSet* tw) {
   const size_t L1 = ((size_t)1 << kMaxLogLen) - 1;
   for (int i = 0; i < 2; ++i) {
@@ -511,6 +546,34 @@ void load_tuning(TuneTable* t) {
 }  // namespace dmi
 
 namespace {
+// The scratch memory of dmul_ex_noalloc: one product's workspace (4N words,
+// N <= kStaticMaxN) followed by its recovery carry maps.  Every device the
+// library runs on holds its own copy (64 MiB + 16 KiB) from the loading of
+// this code object until the process ends.  Host code never uses this name
+// as an address: scratch_address() asks the runtime for the current
+// device's copy once per device and keeps it.
+static __device__ __align__(256) uint64_t scratch[4 * kStaticMaxN + kStaticMapWords];
+
+std::mutex g_scratch_mu;
+std::map<int, uint64_t*> g_scratch;   // device -> its copy of scratch
+
+// `device` must be the current device.
+int scratch_address(int device, uint64_t** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(device);
+  if (it == g_scratch.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return DMUL_EDEVICE;
+    }
+    it = g_scratch.emplace(device, (uint64_t*)p).first;
+  }
+  *out = it->second;
+  return DMUL_OK;
+}
+
 std::mutex g_default_mu;
 std::map<int, dmul_ctx*> g_default;
 
@@ -648,6 +711,8 @@ int dmul_ctx_create(dmul_ctx** out, int device, size_t budget) {
   if (e == hipSuccess) e = hipMemcpy(c->d_div, &dt, sizeof(DivTable), hipMemcpyHostToDevice);
   if (e != hipSuccess) rc = from_hip(e);
   if (!rc) rc = ensure_status(c, 1);
+  if (!rc) rc = prebuild_pass_tables(c);
+  if (!rc) rc = scratch_address(device, &c->scratch);
 
   if (rc) {
     dmul_ctx_destroy(c);
@@ -666,6 +731,7 @@ int dmul_ctx_destroy(dmul_ctx* c) {
   delete c->timing;
   for (auto& kv : c->pass)
     if (kv.second.owned) (void)hipFree(kv.second.dev);
+  if (c->pass_block) (void)hipFree(c->pass_block);
   if (c->ws) (void)hipFree(c->ws);
   if (c->d_roots) (void)hipFree(c->d_roots);
   if (c->d_r3) (void)hipFree(c->d_r3);
@@ -781,6 +847,51 @@ int dmul_debug_residues(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_
   }
   const int rs = dmul_sync(c);
   return rc ? rc : rs;
+}
+
+int dmul_ex_noalloc(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
+                    uint64_t* out, unsigned flags) {
+  if (!c) return DMUL_EINVAL;
+  int rc = check_args(a, na, b, nb, out);
+  if (rc) return rc;
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return DMUL_EDEVICE;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (na == 0 || nb == 0) return from_hip(launch_zero(out, na + nb, c->stream));
+  PlanDev pl;
+  rc = make_plan(na, nb, flags, &pl);
+  if (rc) return rc;
+  if (pl.N > kStaticMaxN) return DMUL_ENOMEM;      // beyond the static scratch
+  TwiddleSet tw;
+  if (!c->scratch || !find_twiddles(c, pl, &tw)) return DMUL_EDEVICE;   // built at creation
+  Work w{};
+  ProdDesc& d = w.one;
+  d.pl = pl;
+  d.a = a;
+  d.b = b;
+  d.out = out;
+  d.ws = c->scratch;
+  d.status = c->d_status;
+  d.rec_sync = (uint32_t*)(c->scratch + 4 * kStaticMaxN);
+  d.nblk = (uint32_t)recover_blocks(pl);
+  d.square = (a == b && na == nb) ? 1 : 0;
+  w.count = 1;
+  const Shape sh{pl.logR, pl.logC, pl.rad3, d.square ? 0 : 1, row_iters_for(c, pl), d.nblk};
+  hipError_t e = hipSuccess;
+  if (c->poison) {
+    e = launch_fill32(d.ws, 2 * workspace_words(pl), kPoison, c->stream);
+    if (e == hipSuccess) e = launch_fill32(d.rec_sync, d.nblk + 1, kPoison, c->stream);
+    if (e != hipSuccess) return from_hip(e);
+  }
+  if (small_fits(pl, 1)) {
+    e = launch_small(w, sh, c->cs, tw, c->d_div, &c->h_div, c->stream, nullptr);
+  } else {
+    e = launch_fused(w, sh, c->cs, tw, c->d_div, c->stream, nullptr);
+    if (e == hipSuccess) e = launch_recover(w, sh, c->cs, c->d_div, &c->h_div, c->stream, nullptr);
+  }
+  rc = from_hip(e);
+  if (rc == DMUL_EDEVICE && c->pending == DMUL_OK) c->pending = rc;
+  return rc;
 }
 
 int dmul_ctx_tune(dmul_ctx* c, uint64_t transform_len, int row_iters) {

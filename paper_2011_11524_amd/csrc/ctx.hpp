@@ -128,6 +128,8 @@ struct dmul_ctx {
   uint64_t* d_roots = nullptr;          // [prime][dir] blocks of 2^kMaxLogLen - 1 words
   uint64_t* d_r3 = nullptr;             // [prime][dir] blocks of kR3TableWords words
   std::map<uint64_t, dmi::PassTables> pass; // by N
+  uint64_t* pass_block = nullptr;       // the tables of every length up to kStaticMaxN, built at creation
+  uint64_t* scratch = nullptr;          // this device's static scratch array (dmul_ex_noalloc)
   uint64_t* ws = nullptr;
   size_t ws_words = 0;
   int* d_status = nullptr;              // [0]: dmul_ex; then one region per batch since dmul_sync
@@ -193,6 +195,7 @@ int make_plan(size_t na, size_t nb, unsigned flags, PlanDev* pl);
 size_t workspace_words(const PlanDev& pl);
 int get_twiddles(dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw);
 bool find_twiddles(const dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw);
+int prebuild_pass_tables(dmul_ctx* ctx);
 int layout_logR(int e, int rad3);
 int ensure_workspace(dmul_ctx* ctx, size_t words);
 int ensure_rec_sync(dmul_ctx* ctx, size_t words);

@@ -17,6 +17,10 @@ constexpr uint64_t kSmallMaxN = 4096;   // whole product in one workgroup up to 
 constexpr uint64_t kSmallSoloMaxN = 2048;  // ... for a lone product (one workgroup vs the device)
 constexpr size_t kSmallMinCount = 8;       // products of a class that make 4096 worth it
 constexpr int kMinK = 13;          // p1*p2 < 10^(3k): three base-10^k parts per coefficient
+// Allocation-free products (dmul_ex_noalloc) run in a static device array of
+// 4 * kStaticMaxN workspace words plus kStaticMapWords words of carry maps.
+constexpr uint64_t kStaticMaxN = (uint64_t)1 << 21;
+constexpr size_t kStaticMapWords = 2048;   // >= (kStaticMaxN / 1024 + 1) 32-bit maps
 constexpr uint64_t kLimbBase = 10000000000000000000ULL;  // 10^19
 
 // Magic multipliers for floor(x / 10^e), x < 2^64, e in [0, 19]:
