@@ -258,6 +258,29 @@ int dmul_spectrum_create(dmul_ctx* ctx, const uint64_t* a, size_t na, size_t nb,
 int dmul_spectrum_destroy(dmul_spectrum* spec);
 size_t dmul_spectrum_bytes(size_t na, size_t nb, unsigned flags);
 
+/* dmul_spectrum_export: the spectrum's transforms in natural frequency
+ * order: out (device, 2N words) receives out[i * N + k] = sum_j x_j xi^(jk)
+ * mod p_(i+1), k < N, where x_j are the operand's base-10^k digit groups
+ * (zero beyond its n_k groups) and xi = g^((p-1)/N) with the generators of
+ * dmul_primes.  The library keeps a transform as an R x C matrix holding
+ * frequency k1 + R k2 at row rev(k1), column rev(k2) (DIF without bit
+ * reversal, Sections 5.4 and 7.4); the export copies it to out and puts it
+ * in order there in place: bit reversal of the rows and of every row's
+ * columns, then the in-place transposition of Section 7.6 (C = R, or
+ * C = 2R: the column permutation rho on every row, then the two R x R
+ * squares), whose row scratch is on chip.  For power-of-two plans with
+ * R >= 32 (N >= 2^10); DMUL_EINVAL otherwise.  Asynchronous on ctx's
+ * stream (dmul_sync completes it). */
+int dmul_spectrum_export(dmul_ctx* ctx, const dmul_spectrum* spec, uint64_t* out);
+
+/* dmul_debug_transpose: transposes the rows x cols matrix of 64-bit words
+ * at data (device, row-major) in place into cols x rows, by the scheme of
+ * Section 7.6 (cols == rows; cols == 2 rows: rho on every row, then the two
+ * squares; rows == 2 cols: the two squares of the cols x rows view, then
+ * rho^-1 on each of its rows).  rows and cols: powers of two in [32, 8192].
+ * Asynchronous on ctx's stream.  Returns DMUL_OK or DMUL_EINVAL. */
+int dmul_debug_transpose(dmul_ctx* ctx, uint64_t* data, size_t rows, size_t cols);
+
 /* dmul_ex_spectrum: like dmul_ex with X given by its spectrum sa (X has
  * sa's na limbs), and Y given either by limbs (b, nb: device pointer, sb
  * NULL) or by its spectrum sb (then b must be NULL and nb equal sb's limb

@@ -37,7 +37,8 @@ EXPORTS = ("dmul", "dmul_ctx_create", "dmul_ctx_destroy", "dmul_ctx_set_stream",
            "dmul_host", "dmul_primes", "dmul_debug_residues", "dmul_version", "dmul_ctx_profile",
            "dmul_ctx_profile_read", "dmul_phase_name", "dmul_ctx_profile_events", "dmul_ctx_tune",
            "dmul_spectrum_create", "dmul_spectrum_destroy", "dmul_spectrum_bytes", "dmul_ex_spectrum",
-           "dmul_batch_ex", "dmul_ctx_timing", "dmul_ctx_timing_read", "dmul_ex_noalloc")
+           "dmul_batch_ex", "dmul_ctx_timing", "dmul_ctx_timing_read", "dmul_ex_noalloc",
+           "dmul_spectrum_export", "dmul_debug_transpose")
 
 
 class DmulError(RuntimeError):
@@ -121,6 +122,8 @@ def lib():
     L.dmul_batch_ex.argtypes = [vp, sz, ctypes.POINTER(vp), ctypes.POINTER(sz), ctypes.POINTER(vp),
                                 ctypes.POINTER(vp), ctypes.POINTER(sz), ctypes.POINTER(vp),
                                 ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int32), ctypes.c_uint]
+    L.dmul_spectrum_export.argtypes = [vp, vp, vp]
+    L.dmul_debug_transpose.argtypes = [vp, vp, sz, sz]
     L.dmul_phase_name.argtypes = [ctypes.c_int]
     L.dmul_phase_name.restype = ctypes.c_char_p
     _lib = L
@@ -315,6 +318,26 @@ class Context:
         self.mul_spectrum_async(sa, b, out, sb, force_k, pow2)
         self.sync()
         return out
+
+    def spectrum_export(self, s: "Spectrum"):
+        """The spectrum in natural frequency order: a (2, N) uint64 tensor,
+        row i the transform modulo prime i (power-of-two plans, N >= 2^10)."""
+        N = plan(s.na, s.nb_plan, s.flags & 0x1F, bool(s.flags & DMUL_FLAG_POW2)).N
+        out = torch.empty(2 * N, dtype=torch.uint64, device=f"cuda:{self.device}")
+        rc = self._lib.dmul_spectrum_export(self._h, s._h, ctypes.c_void_p(out.data_ptr()))
+        if rc:
+            raise DmulError(rc, "dmul_spectrum_export")
+        self.sync()
+        return out.view(2, N)
+
+    def transpose(self, t, rows: int, cols: int):
+        """In-place transposition of a rows x cols uint64 CUDA tensor (its
+        storage becomes cols x rows); blocking."""
+        rc = self._lib.dmul_debug_transpose(self._h, ctypes.c_void_p(t.data_ptr()), int(rows), int(cols))
+        if rc:
+            raise DmulError(rc, "dmul_debug_transpose")
+        self.sync()
+        return t.view(cols, rows)
 
     # -- batches -------------------------------------------------------------
     def prepare_batch(self, pairs: Sequence, outs: Sequence) -> "PreparedBatch":

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdmul.so")
-SOURCES = ["api.hip", "batch.hip", "ntt.hip", "carry.hip", "small.hip"]
+SOURCES = ["api.hip", "batch.hip", "ntt.hip", "carry.hip", "small.hip", "transpose.hip"]
 HEADERS = ["field.hpp", "internal.hpp", "ctx.hpp", "batch.hpp", "ntt_dev.hpp", "rec_dev.hpp"]
 
 HIPCC_FLAGS = [

@@ -1083,6 +1083,31 @@ int dmul_spectrum_destroy(dmul_spectrum* s) {
   return DMUL_OK;
 }
 
+int dmul_spectrum_export(dmul_ctx* c, const dmul_spectrum* s, uint64_t* out) {
+  if (!c || !s || !out || s->device != c->device) return DMUL_EINVAL;
+  if (s->pl.rad3 || s->pl.logR < 5) return DMUL_EINVAL;
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return DMUL_EDEVICE;
+  std::lock_guard<std::mutex> lk(c->mu);
+  const uint64_t N = s->pl.N;
+  hipError_t e = hipMemcpyAsync(out, s->dev, 2 * N * sizeof(uint64_t), hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return from_hip(e);
+  for (int pi = 0; pi < 2; ++pi) {
+    const int rc = transpose_inplace(out + pi * N, (uint64_t)1 << s->pl.logR, (uint64_t)1 << s->pl.logC,
+                                     true, c->stream);
+    if (rc) return rc;
+  }
+  return DMUL_OK;
+}
+
+int dmul_debug_transpose(dmul_ctx* c, uint64_t* data, size_t rows, size_t cols) {
+  if (!c || !data) return DMUL_EINVAL;
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return DMUL_EDEVICE;
+  std::lock_guard<std::mutex> lk(c->mu);
+  return transpose_inplace(data, rows, cols, false, c->stream);
+}
+
 int dmul_ex_spectrum(dmul_ctx* c, const dmul_spectrum* sa, const uint64_t* b, size_t nb,
                      const dmul_spectrum* sb, uint64_t* out, unsigned flags) {
   if (!c || !sa || !out) return DMUL_EINVAL;

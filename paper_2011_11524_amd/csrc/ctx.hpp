@@ -197,6 +197,9 @@ int get_twiddles(dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw);
 bool find_twiddles(const dmul_ctx* ctx, const PlanDev& pl, TwiddleSet* tw);
 int prebuild_pass_tables(dmul_ctx* ctx);
 int layout_logR(int e, int rad3);
+// rows x cols -> cols x rows in place on `stream` (transpose.hip); with
+// bitrev, the row order and the columns of every row bit-reversed first.
+int transpose_inplace(uint64_t* data, uint64_t rows, uint64_t cols, bool bitrev, hipStream_t stream);
 int ensure_workspace(dmul_ctx* ctx, size_t words);
 int ensure_rec_sync(dmul_ctx* ctx, size_t words);
 int row_iters_for(const dmul_ctx* ctx, const PlanDev& pl);
