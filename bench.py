@@ -105,6 +105,43 @@ def traffic_for(kernel: str, per_launch_units: str):
     return ent.get("bytes_per_launch")
 
 
+# SIMDs of the MI355X (256 CUs x 4) and the clock the VALU peak assumes; a
+# wave64 VALU instruction occupies its SIMD for 4 cycles (one quad-cycle).
+SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
+
+
+def counters_for(kernel: str):
+    """rocprofv3 SQ counters of `kernel` in the C2 product
+    (profiles/c2_10m_counters.json), if they were taken on the current
+    kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "c2_10m_counters.json")
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if data.get("source_hash") != kernel_source_hash():
+        return None
+    return data.get("kernels", {}).get(kernel)
+
+
+def valu_measured(kernel: str, live_s: float):
+    """VALU issue of `kernel` from its counters: the fraction of SIMD cycles
+    that issued a VALU instruction (SQ_ACTIVE_INST_VALU quad-cycles x 4 over
+    1024 SIMDs x 2.4 GHz x the counted dispatch's duration), and the lane
+    instructions per second at this run's live duration."""
+    c = counters_for(kernel)
+    if not c or "SQ_ACTIVE_INST_VALU" not in c:
+        return None
+    dur = c["ns_valu"] * 1e-9
+    return {"valu_busy": round(c["SQ_ACTIVE_INST_VALU"] * 4 / (SIMDS * CLOCK_HZ * dur), 4),
+            "valu_insts_per_launch": c["SQ_INSTS_VALU"],
+            "lane_instr_tops": round(c["SQ_INSTS_VALU"] * 64 / live_s / 1e12, 3),
+            "lds_bank_conflict_per_lds_cycle": round(c["SQ_LDS_BANK_CONFLICT"] / max(1.0, c["SQ_ACTIVE_INST_LDS"]), 3),
+            "source": "profiles/c2_10m_counters.json"}
+
+
 def cpu_baseline(a, b, budget_s: float, max_products: int):
     import oracle
     times = []
@@ -474,13 +511,21 @@ def main() -> int:
                 "achieved": round(d["valu_tops"], 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "TOP/s", "frac": round(d["valu_tops"] / VALU_PEAK_TOPS, 4),
                 "ops_per_launch": ops_dom, "bytes_per_launch": bytes_dom,
-                "traffic": traffic_for(dominant, "bytes")}
+                "traffic": traffic_for(dominant, "bytes"),
+                # measured beside the op model: VALU issue from the kernel's counters
+                "measured": valu_measured(dominant, d["avg_us"] * 1e-6)}
     ntt = [k for k in ("fwd_cols", "fwd_rows", "rows", "inv_rows", "inv_cols") if k in phases]
     ntt_s = sum(phases[k]["avg_us"] for k in ntt) / 1e6
     ntt_bytes = sum(work[k][1] for k in ntt)
+    # the survey's plain two-pass byte model: 176 N (2 primes x (2 forward x
+    # 24N + inverse 40N)), without this build's fused row pass
+    plain_bytes = 176 * pl.N
     hbm = {"ntt_phases_gbs": round(ntt_bytes / ntt_s / 1e9, 1), "peak": HBM_PEAK_GBS,
            "frac": round(ntt_bytes / ntt_s / 1e9 / HBM_PEAK_GBS, 4), "ntt_bytes": ntt_bytes,
-           "ntt_us": round(ntt_s * 1e6, 2)}
+           "ntt_us": round(ntt_s * 1e6, 2),
+           "bytes_model": "this build's passes (fused rows): 16(na+nb) + 8AN + 8AN + 16N + 32N",
+           "plain_176N": {"bytes": plain_bytes, "gbs": round(plain_bytes / ntt_s / 1e9, 1),
+                          "frac": round(plain_bytes / ntt_s / 1e9 / HBM_PEAK_GBS, 4)}}
 
     got = out.cpu().numpy()
     result = {

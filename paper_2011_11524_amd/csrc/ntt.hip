@@ -70,9 +70,15 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
   using G = Geometry<LOGR, LOGE>;
   constexpr int R = G::L;
   constexpr int NTH = T * G::NT;                 // threads
-  constexpr int PER = (R * T + NTH - 1) / NTH;   // tile points per thread
+  constexpr int PER = R * T / NTH;               // tile points per thread (2^LOGE)
   constexpr int TS = Tile<T, R3>::TS;
   constexpr bool kWave = G::NT <= 64;            // each column within one wavefront
+  // The DIF stage on the top bit pairs rows r and r + R/2, which are the
+  // thread's points s and s + PER/2.  Where the rounds of LOGE bits would
+  // leave a round of that bit alone, the stage is done as the tile is
+  // written to LDS, and the rounds cover the bits below it.
+  constexpr bool kTop = LOGR % LOGE == 1 && LOGR > 1;
+  static_assert(PER * NTH == R * T, "a tile is whole rows of whole columns");
   extern __shared__ uint64_t lds[];
   uint64_t* troots = lds + T * G::STRIDE;        // [prime][R/2]
   const ProdDesc d = load_desc(w);
@@ -95,70 +101,104 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
     troots[i] = tw.len_fwd[p][root_table_offset(LOGR) + e];
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < R * T; q += NTH) {
-    const int row = q / T, sl = q % T;
-    lds[sl * G::STRIDE + lds_pos<LOGE>(row)] =
-        tile.valid(sl) ? split_group(src, nl, ng, (uint64_t)row * C + tile.column(sl), d.pl.k, dt, d.status)
-                       : 0;
-  }
-  __syncthreads();
-  uint64_t v[PER];   // the split tile, kept for the second prime
+  // the split tile, in registers for both primes: point s of the thread is
+  // row threadIdx.x / T + s * NT of column slot threadIdx.x % T; every load
+  // of the thread is issued before the divisions that use them
+  uint64_t v[PER];
+  {
+    int bad = 0;
 #pragma unroll
-  for (int s = 0; s < PER; ++s) {
-    const int q = threadIdx.x + s * NTH;
-    v[s] = q < R * T ? lds[(q % T) * G::STRIDE + lds_pos<LOGE>(q / T)] : 0;
+    for (int s = 0; s < PER; ++s) {
+      const int q = threadIdx.x + s * NTH;
+      const int row = q / T, sl = q % T;
+      v[s] = tile.valid(sl) ? split_group_nf(src, nl, ng, (uint64_t)row * C + tile.column(sl), d.pl.k, dt, bad)
+                            : 0;
+    }
+    if (bad) atomicOr(d.status, 1);
   }
-  // those reads cross columns: every thread has its copy before the first
-  // round of any column's transform overwrites the tile
-  __syncthreads();
   const int col = threadIdx.x / G::NT, t = threadIdx.x % G::NT;
 #pragma unroll 1
   for (int pi = 0; pi < 2; ++pi) {
     const Prime P = cs.P[pi];
+    const uint64_t* rts = troots + pi * (R / 2);
     uint64_t* dst = d.ws + (size_t)(2 * op + pi) * N;
-    if (pi == 1) {
+    // the tile of this prime (the groups are below 10^k < p: the same
+    // residues for both primes)
+    if constexpr (kTop) {
+#pragma unroll
+      for (int s = 0; s < PER / 2; ++s) {
+        const int q = threadIdx.x + s * NTH;
+        const int row = q / T, sl = q % T;       // row < R/2; v[s + PER/2] is row + R/2
+        const uint64_t a = v[s], b = v[s + PER / 2];
+        lds[sl * G::STRIDE + lds_pos<LOGE>(row)] = add_mod(a, b, P);
+        lds[sl * G::STRIDE + lds_pos<LOGE>(row + R / 2)] = mont_mul(sub_lazy(a, b, P), rts[row], P);
+      }
+    } else {
 #pragma unroll
       for (int s = 0; s < PER; ++s) {
         const int q = threadIdx.x + s * NTH;
-        if (q < R * T) lds[(q % T) * G::STRIDE + lds_pos<LOGE>(q / T)] = v[s];
+        lds[(q % T) * G::STRIDE + lds_pos<LOGE>(q / T)] = v[s];
       }
-      __syncthreads();
     }
-    lds_transform<LOGR, LOGE, false, kWave>(lds + col * G::STRIDE, troots + pi * (R / 2), P, t, true);
+    __syncthreads();
+    if constexpr (kTop) {
+      DifBelow<LOGR, LOGE, LOGR - 1, kWave>::run(lds + col * G::STRIDE, rts, P, t);
+    } else {
+      lds_transform<LOGR, LOGE, false, kWave>(lds + col * G::STRIDE, rts, P, t, true);
+    }
     if constexpr (kWave) __syncthreads();
+    // Inter-pass factor xi_N^(rev(row) * j) for column j.  Each thread takes
+    // one column (slot) and a run of consecutive rv = rev(row), so its
+    // factors form a chain f(rv + 1) = f(rv) * xi^j: one table product to
+    // start it, one Montgomery product per row after that.
     if constexpr (!R3) {
-      for (int q = threadIdx.x; q < R * T; q += NTH) {
-        const int row = q / T, c = q % T;
-        if (!tile.valid(c)) continue;
+      constexpr int U = NTH / T;                 // threads per column
+      constexpr int PP = (R + U - 1) / U;        // rows per thread
+      const int c = threadIdx.x % T, u = threadIdx.x / T;
+      const int v0 = u * PP, v1 = v0 + PP < R ? v0 + PP : R;
+      if (tile.valid(c) && v0 < v1) {
         const uint32_t j = (uint32_t)tile.column(c);
-        const uint32_t e = __umul24(bitrev(row, LOGR), j);     // < N <= 2^26
-        uint64_t x = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
-        x = mont_mul(x, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], e, lb, P), P);
-        dst[(uint32_t)row * (uint32_t)C + j] = x;
+        const uint64_t step = tw.lo_fwd[pi][j];                       // xi^j, j < C <= 2^lb
+        uint64_t f = pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], (uint32_t)v0 * j, lb, P);   // < N
+        for (int rv = v0; rv < v1; ++rv) {
+          const uint32_t row = bitrev((uint32_t)rv, LOGR);
+          dst[row * (uint32_t)C + j] = mont_mul(lds[c * G::STRIDE + lds_pos<LOGE>(row)], f, P);
+          f = mont_mul(f, step, P);
+        }
       }
     } else {
       const uint64_t* w3 = tw.r3_fwd[pi] + r3_table_offset(d.pl.logC);
-      const uint64_t M = tile.M;
-      for (int q = threadIdx.x; q < R * TS; q += NTH) {
-        const int row = q / TS, c = q % TS;
-        if (!tile.valid(c)) continue;
+      const uint32_t M = (uint32_t)tile.M;
+      constexpr int U = NTH / TS;                // threads per column triple
+      constexpr int PP = (R + U - 1) / U;
+      const int c = threadIdx.x % TS, u = threadIdx.x / TS;
+      const int v0 = u * PP, v1 = v0 + PP < R ? v0 + PP : R;
+      if (tile.valid(c) && v0 < v1) {
         const uint32_t qc = (uint32_t)tile.first + c;
-        const uint32_t rv = bitrev(row, LOGR);
-        const uint32_t e0 = __umul24(rv, qc), eM = __umul24(rv, (uint32_t)M);   // rv*(s*M + qc) < N
-        const int o = lds_pos<LOGE>(row);
-        uint64_t x0 = lds[c * G::STRIDE + o];
-        uint64_t x1 = lds[(TS + c) * G::STRIDE + o];
-        uint64_t x2 = lds[(2 * TS + c) * G::STRIDE + o];
-        x0 = mont_mul(x0, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], e0, lb, P), P);
-        x1 = mont_mul(x1, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], e0 + eM, lb, P), P);
-        x2 = mont_mul(x2, pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], e0 + 2 * eM, lb, P), P);
-        dft3(x0, x1, x2, cs.kappa[pi][0], P);
-        x1 = mont_mul(x1, w3[qc], P);
-        x2 = mont_mul(x2, w3[2 * qc], P);
-        uint64_t* rowp = dst + ((uint32_t)row * (uint32_t)C + qc);
-        rowp[0] = x0;
-        rowp[M] = x1;
-        rowp[2 * M] = x2;
+        const uint64_t w31 = w3[qc], w32 = w3[2 * qc];
+        uint64_t f[3], st[3];
+#pragma unroll
+        for (int sx = 0; sx < 3; ++sx) {
+          const uint32_t j = qc + (uint32_t)sx * M;                  // < C = 3M < 2^lb
+          st[sx] = tw.lo_fwd[pi][j];
+          f[sx] = pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], (uint32_t)v0 * j, lb, P);
+        }
+        for (int rv = v0; rv < v1; ++rv) {
+          const uint32_t row = bitrev((uint32_t)rv, LOGR);
+          const int o = lds_pos<LOGE>((int)row);
+          uint64_t x0 = mont_mul(lds[c * G::STRIDE + o], f[0], P);
+          uint64_t x1 = mont_mul(lds[(TS + c) * G::STRIDE + o], f[1], P);
+          uint64_t x2 = mont_mul(lds[(2 * TS + c) * G::STRIDE + o], f[2], P);
+          dft3(x0, x1, x2, cs.kappa[pi][0], P);
+          x1 = mont_mul(x1, w31, P);
+          x2 = mont_mul(x2, w32, P);
+          uint64_t* rowp = dst + (row * (uint32_t)C + qc);
+          rowp[0] = x0;
+          rowp[M] = x1;
+          rowp[2 * M] = x2;
+#pragma unroll
+          for (int sx = 0; sx < 3; ++sx) f[sx] = mont_mul(f[sx], st[sx], P);
+        }
       }
     }
     __syncthreads();
@@ -350,7 +390,12 @@ __global__ void __launch_bounds__((T * Geometry<LOGR, LOGE>::NT))
 k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   using G = Geometry<LOGR, LOGE>;
   constexpr int TS = Tile<T, R3>::TS;
+  constexpr int NTH = T * G::NT;
   constexpr bool kWave = G::NT <= 64;            // each column within one wavefront
+  // DIT rounds go bottom bit up; where the rounds of LOGE bits would leave
+  // the top bit alone, its stage (rows r and r + R/2) is done as the tile is
+  // stored to global memory.
+  constexpr bool kTop = LOGR % LOGE == 1 && LOGR > 1;
   extern __shared__ uint64_t lds[];
   uint64_t* troots = lds + T * G::STRIDE;
   const ProdDesc d = load_desc(w);
@@ -359,42 +404,74 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   uint64_t* X = d.ws + (size_t)pi * d.pl.N;
   const Tile<T, R3> tile(xcd_tile(blockIdx.x, gridDim.x), d.pl.logC, d.pl.rad3);
   const uint64_t C = tile.C;
+  const uint32_t N = (uint32_t)d.pl.N;
   const int lb = pass_split_bits(d.pl.logC, d.pl.rad3);
   constexpr int R = G::L;
 
   for (int i = threadIdx.x; i < R / 2; i += blockDim.x)
     troots[i] = tw.len_inv[pi][root_table_offset(LOGR) + i];
+  // Inter-pass factor with the scale, xi_N^(-rev(row) * j) * R^2 N^-1: per
+  // thread one column (slot) and a run of consecutive rv = rev(row), the
+  // factors a chain f(rv + 1) = f(rv) * xi^-j (xi^-j = xi^(N - j)).
+  auto step_inv = [&](uint32_t j) {
+    return j ? pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], N - j, lb, P) : tw.lo_fwd[pi][0];
+  };
   if constexpr (!R3) {
-    for (int q = threadIdx.x; q < R * T; q += blockDim.x) {
-      const int row = q / T, c = q % T;
-      uint64_t v = 0;
-      if (tile.valid(c)) {
-        const uint32_t j = (uint32_t)tile.column(c);
-        const uint32_t e = __umul24(bitrev(row, LOGR), j);     // < N <= 2^26
-        v = X[(uint32_t)row * (uint32_t)C + j];
-        v = mont_mul(v, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], e, lb, P), P);
+    constexpr int U = NTH / T;
+    constexpr int PP = (R + U - 1) / U;
+    const int c = threadIdx.x % T, u = threadIdx.x / T;
+    const int v0 = u * PP, v1 = v0 + PP < R ? v0 + PP : R;
+    const uint32_t j = (uint32_t)tile.column(c);
+    const bool ok = tile.valid(c);
+    uint64_t f = 0, st = 0;
+    if (ok && v0 < v1) {
+      st = step_inv(j);
+      f = pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], (uint32_t)v0 * j, lb, P);
+    }
+    for (int rv = v0; rv < v1; ++rv) {
+      const uint32_t row = bitrev((uint32_t)rv, LOGR);
+      uint64_t x = 0;
+      if (ok) {
+        x = mont_mul(X[row * (uint32_t)C + j], f, P);
+        f = mont_mul(f, st, P);
       }
-      lds[c * G::STRIDE + lds_pos<LOGE>(row)] = v;
+      lds[c * G::STRIDE + lds_pos<LOGE>((int)row)] = x;
     }
   } else {
     const uint64_t* w3 = tw.r3_inv[pi] + r3_table_offset(d.pl.logC);
-    const uint64_t M = tile.M;
-    for (int q = threadIdx.x; q < R * TS; q += blockDim.x) {
-      const int row = q / TS, c = q % TS;
-      const int o = lds_pos<LOGE>(row);
+    const uint32_t M = (uint32_t)tile.M;
+    constexpr int U = NTH / TS;
+    constexpr int PP = (R + U - 1) / U;
+    const int c = threadIdx.x % TS, u = threadIdx.x / TS;
+    const int v0 = u * PP, v1 = v0 + PP < R ? v0 + PP : R;
+    const bool ok = tile.valid(c);
+    const uint32_t qc = (uint32_t)tile.first + c;
+    uint64_t w31 = 0, w32 = 0, f[3] = {0, 0, 0}, st[3] = {0, 0, 0};
+    if (ok && v0 < v1) {
+      w31 = w3[qc];
+      w32 = w3[2 * qc];
+#pragma unroll
+      for (int sx = 0; sx < 3; ++sx) {
+        const uint32_t j = qc + (uint32_t)sx * M;
+        st[sx] = step_inv(j);
+        f[sx] = pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], (uint32_t)v0 * j, lb, P);
+      }
+    }
+    for (int rv = v0; rv < v1; ++rv) {
+      const uint32_t row = bitrev((uint32_t)rv, LOGR);
+      const int o = lds_pos<LOGE>((int)row);
       uint64_t x0 = 0, x1 = 0, x2 = 0;
-      if (tile.valid(c)) {
-        const uint32_t qc = (uint32_t)tile.first + c;
-        const uint64_t* rowp = X + ((uint32_t)row * (uint32_t)C + qc);
+      if (ok) {
+        const uint64_t* rowp = X + (row * (uint32_t)C + qc);
         x0 = rowp[0];
-        x1 = mont_mul(rowp[M], w3[qc], P);
-        x2 = mont_mul(rowp[2 * M], w3[2 * qc], P);
+        x1 = mont_mul(rowp[M], w31, P);
+        x2 = mont_mul(rowp[2 * M], w32, P);
         dft3(x0, x1, x2, cs.kappa[pi][1], P);
-        const uint32_t rv = bitrev(row, LOGR);
-        const uint32_t e0 = __umul24(rv, qc), eM = __umul24(rv, (uint32_t)M);   // rv*(s*M + qc) < N
-        x0 = mont_mul(x0, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], e0, lb, P), P);
-        x1 = mont_mul(x1, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], e0 + eM, lb, P), P);
-        x2 = mont_mul(x2, pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], e0 + 2 * eM, lb, P), P);
+        x0 = mont_mul(x0, f[0], P);
+        x1 = mont_mul(x1, f[1], P);
+        x2 = mont_mul(x2, f[2], P);
+#pragma unroll
+        for (int sx = 0; sx < 3; ++sx) f[sx] = mont_mul(f[sx], st[sx], P);
       }
       lds[c * G::STRIDE + o] = x0;
       lds[(TS + c) * G::STRIDE + o] = x1;
@@ -403,12 +480,26 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   }
   __syncthreads();
   const int col = threadIdx.x / G::NT, t = threadIdx.x % G::NT;
-  lds_transform<LOGR, LOGE, true, kWave>(lds + col * G::STRIDE, troots, P, t, true);
-  if constexpr (kWave) __syncthreads();
-  for (int q = threadIdx.x; q < R * T; q += blockDim.x) {
-    const int row = q / T, c = q % T;
-    if (tile.valid(c))
-      X[(uint32_t)row * (uint32_t)C + (uint32_t)tile.column(c)] = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
+  if constexpr (kTop) {
+    DitFrom<LOGR, LOGE, 0, LOGR - 1, kWave>::run(lds + col * G::STRIDE, troots, P, t);
+    if constexpr (kWave) __syncthreads();
+    for (int q = threadIdx.x; q < (R / 2) * T; q += blockDim.x) {
+      const int row = q / T, c = q % T;
+      if (!tile.valid(c)) continue;
+      const uint64_t x = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
+      const uint64_t y = mont_mul(lds[c * G::STRIDE + lds_pos<LOGE>(row + R / 2)], troots[row], P);
+      const uint32_t j = (uint32_t)tile.column(c);
+      X[(uint32_t)row * (uint32_t)C + j] = add_mod(x, y, P);
+      X[(uint32_t)(row + R / 2) * (uint32_t)C + j] = sub_mod(x, y, P);
+    }
+  } else {
+    lds_transform<LOGR, LOGE, true, kWave>(lds + col * G::STRIDE, troots, P, t, true);
+    if constexpr (kWave) __syncthreads();
+    for (int q = threadIdx.x; q < R * T; q += blockDim.x) {
+      const int row = q / T, c = q % T;
+      if (tile.valid(c))
+        X[(uint32_t)row * (uint32_t)C + (uint32_t)tile.column(c)] = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
+    }
   }
 }
 

@@ -151,6 +151,37 @@ struct RoundRange {
   }
 };
 
+// DIF rounds over bits [0, TOP) of a 2^LOGL-point transform, top bits
+// first, LOGE bits per round (the last may be shorter): the rest of a DIF
+// whose stages on bits >= TOP were done elsewhere.  A round_sync follows
+// every round.
+template <int LOGL, int LOGE, int TOP, bool WAVE>
+struct DifBelow {
+  static __device__ __forceinline__ void run(uint64_t* lds, const uint64_t* __restrict__ tw,
+                                             const Prime& P, int t) {
+    if constexpr (TOP > 0) {
+      constexpr int LO = TOP > LOGE ? TOP - LOGE : 0;
+      Round<LOGL, LOGE, false, LO, TOP - LO>::run(lds, tw, P, t);
+      round_sync<WAVE>();
+      DifBelow<LOGL, LOGE, LO, WAVE>::run(lds, tw, P, t);
+    }
+  }
+};
+
+// DIT rounds over bits [LO, TOP), bottom bits first, LOGE bits per round.
+template <int LOGL, int LOGE, int LO, int TOP, bool WAVE>
+struct DitFrom {
+  static __device__ __forceinline__ void run(uint64_t* lds, const uint64_t* __restrict__ tw,
+                                             const Prime& P, int t) {
+    if constexpr (LO < TOP) {
+      constexpr int HI = LO + LOGE < TOP ? LO + LOGE : TOP;
+      Round<LOGL, LOGE, true, LO, HI - LO>::run(lds, tw, P, t);
+      round_sync<WAVE>();
+      DitFrom<LOGL, LOGE, HI, TOP, WAVE>::run(lds, tw, P, t);
+    }
+  }
+};
+
 // In-LDS transform of 2^LOGL points (DIF natural->bit-reversed, or DIT
 // bit-reversed->natural), run by the workgroup; `active` threads own a
 // transform, the others only take part in the synchronisation.  With WAVE
@@ -188,6 +219,29 @@ __device__ __forceinline__ uint64_t split_group(const uint64_t* __restrict__ lim
   } else {
     const uint64_t hi = L + 1 < nl ? limbs[L + 1] : 0;
     if (hi >= kLimbBase) atomicOr(status, 1);
+    const int need = k - have;
+    const uint64_t top = hi - div_pow10(hi, need, dt) * dt->pow10[need];
+    x += top * dt->pow10[have];
+  }
+  return x;
+}
+
+// split_group without the atomic: a limb >= 10^19 sets `bad` (reported once by the caller)
+__device__ __forceinline__ uint64_t split_group_nf(const uint64_t* __restrict__ limbs, uint64_t nl,
+                                                   uint64_t ng, uint64_t g, int k,
+                                                   const DivTable* __restrict__ dt, int& bad) {
+  if (g >= ng) return 0;
+  const uint64_t d0 = g * (uint64_t)k;
+  const uint64_t L = __umul64hi(d0, 0xD79435E50D79435FULL) >> 4;
+  const int o = (int)(d0 - L * 19);
+  const uint64_t lo = L < nl ? limbs[L] : 0;
+  const uint64_t hi = L + 1 < nl ? limbs[L + 1] : 0;
+  const int have = 19 - o;
+  bad |= (lo >= kLimbBase) | (have < k && hi >= kLimbBase);
+  uint64_t x = div_pow10(lo, o, dt);
+  if (have >= k) {
+    x -= div_pow10(x, k, dt) * dt->pow10[k];
+  } else {
     const int need = k - have;
     const uint64_t top = hi - div_pow10(hi, need, dt) * dt->pow10[need];
     x += top * dt->pow10[have];
