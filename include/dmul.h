@@ -26,6 +26,14 @@
  * 5, 6, 7), and every coefficient is recovered by the two-prime CRT and
  * carried into base 10^19 (Section 8.2).  The result is bit-exact.
  *
+ * The same interface is built twice: libdmul.so as above, and
+ * libdmul_lazy.so with the two largest such primes below 2^62 = mu/4,
+ *   p1 = 4611685318347718657, p2 = 4611685692009873409,
+ * whose butterflies keep values in the redundant ranges [0, 2p) and
+ * [0, 4p) between stages (Sections 8.3, 9); its digit-group bound uses its
+ * own p1 * p2 (about 2^124), so k may be one less.  dmul_primes and
+ * dmul_plan report the primes and plans of the build they belong to.
+ *
  * Pointers: unless a function says "host", every limb pointer is a DEVICE
  * pointer (HBM, e.g. a torch tensor's data_ptr()) on the context's device.
  * The caller owns a, b and out; the library never frees them and does not

@@ -20,7 +20,14 @@ except Exception:  # pragma: no cover - torch is part of the image
     torch = None
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdmul.so")
+# Two builds of the same sources: the default one (primes below 2^63,
+# canonical residues) and the redundant-range one (primes below 2^62,
+# butterfly values kept in [0, 2p) / [0, 4p)).  DMUL_LIB=lazy makes the
+# second the default of this module.
+LIB_PATHS = {"default": os.path.join(_HERE, "libdmul.so"),
+             "lazy": os.path.join(_HERE, "libdmul_lazy.so")}
+DEFAULT_VARIANT = "lazy" if os.environ.get("DMUL_LIB", "") == "lazy" else "default"
+LIB_PATH = LIB_PATHS[DEFAULT_VARIANT]
 
 DMUL_OK = 0
 DMUL_EINVAL = -1
@@ -70,18 +77,21 @@ class Plan:
     factor: int
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    """Load libdmul.so (raises if it has not been built)."""
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+def lib(variant: str | None = None):
+    """Load a build of the library ("default": libdmul.so, "lazy":
+    libdmul_lazy.so; None: the module's default); raises if it has not been
+    built."""
+    variant = variant or DEFAULT_VARIANT
+    if variant in _libs:
+        return _libs[variant]
+    path = LIB_PATHS[variant]
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() "
                            "or python paper_2011_11524_amd/build.py")
-    L = ctypes.CDLL(LIB_PATH)
+    L = ctypes.CDLL(path)
     u64p = ctypes.POINTER(ctypes.c_uint64)
     vp = ctypes.c_void_p
     sz = ctypes.c_size_t
@@ -126,7 +136,7 @@ def lib():
     L.dmul_debug_transpose.argtypes = [vp, vp, sz, sz]
     L.dmul_phase_name.argtypes = [ctypes.c_int]
     L.dmul_phase_name.restype = ctypes.c_char_p
-    _lib = L
+    _libs[variant] = L
     return L
 
 
@@ -141,16 +151,16 @@ def flags_for(force_k: int = 0, pow2: bool = False) -> int:
     return (int(force_k) & 0x1F) | (DMUL_FLAG_POW2 if pow2 else 0)
 
 
-def primes() -> tuple[list[int], list[int]]:
+def primes(variant: str | None = None) -> tuple[list[int], list[int]]:
     p = (ctypes.c_uint64 * 2)()
     g = (ctypes.c_uint64 * 2)()
-    lib().dmul_primes(p, g)
+    lib(variant).dmul_primes(p, g)
     return [int(p[0]), int(p[1])], [int(g[0]), int(g[1])]
 
 
-def plan(na: int, nb: int, force_k: int = 0, pow2: bool = False) -> Plan:
+def plan(na: int, nb: int, force_k: int = 0, pow2: bool = False, variant: str | None = None) -> Plan:
     info = _PlanInfo()
-    rc = lib().dmul_plan(int(na), int(nb), flags_for(force_k, pow2), ctypes.byref(info))
+    rc = lib(variant).dmul_plan(int(na), int(nb), flags_for(force_k, pow2), ctypes.byref(info))
     if rc:
         raise DmulError(rc, "dmul_plan")
     return Plan(info.k, info.log2_n, info.log2_rows, info.log2_cols, info.groups_a,
@@ -200,8 +210,9 @@ class Context:
     """A dmul context: device tables, workspace, a stream (default: torch's
     current stream on the device at creation time)."""
 
-    def __init__(self, device: int = 0, budget_bytes: int = 0, stream=None):
-        self._lib = lib()
+    def __init__(self, device: int = 0, budget_bytes: int = 0, stream=None, variant: str | None = None):
+        self.variant = variant or DEFAULT_VARIANT
+        self._lib = lib(self.variant)
         self._pending = []          # batches enqueued since the last sync
         h = ctypes.c_void_p()
         rc = self._lib.dmul_ctx_create(ctypes.byref(h), int(device), int(budget_bytes))
@@ -322,7 +333,7 @@ class Context:
     def spectrum_export(self, s: "Spectrum"):
         """The spectrum in natural frequency order: a (2, N) uint64 tensor,
         row i the transform modulo prime i (power-of-two plans, N >= 2^10)."""
-        N = plan(s.na, s.nb_plan, s.flags & 0x1F, bool(s.flags & DMUL_FLAG_POW2)).N
+        N = plan(s.na, s.nb_plan, s.flags & 0x1F, bool(s.flags & DMUL_FLAG_POW2), self.variant).N
         out = torch.empty(2 * N, dtype=torch.uint64, device=f"cuda:{self.device}")
         rc = self._lib.dmul_spectrum_export(self._h, s._h, ctypes.c_void_p(out.data_ptr()))
         if rc:

@@ -8,6 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdmul.so")
+# the same sources with primes below 2^62 and redundant-range butterflies
+LIB_LAZY = os.path.join(HERE, "libdmul_lazy.so")
 SOURCES = ["api.hip", "batch.hip", "ntt.hip", "carry.hip", "small.hip", "transpose.hip"]
 HEADERS = ["field.hpp", "internal.hpp", "ctx.hpp", "batch.hpp", "ntt_dev.hpp", "rec_dev.hpp"]
 
@@ -39,30 +41,36 @@ def stale() -> bool:
 
 
 def build(verbose: bool = False) -> str:
-    """Compiles every source to an object (in parallel), then links them."""
+    """Compiles every source to an object (in parallel), once for each
+    library, then links them: libdmul.so and libdmul_lazy.so."""
     import concurrent.futures
     import tempfile
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    libs = ((LIB, []), (LIB_LAZY, ["-DDMUL_LAZY_FIELD=1"]))
     with tempfile.TemporaryDirectory(prefix="dmul_build_") as tmpdir:
-        def compile_one(src: str) -> str:
-            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
-            cmd = [hipcc()] + compile_flags + inc + ["-c", src, "-o", obj]
+        def compile_one(job):
+            li, src = job
+            obj = os.path.join(tmpdir, f"{li}_{os.path.basename(src)}.o")
+            cmd = [hipcc()] + compile_flags + libs[li][1] + inc + ["-c", src, "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             res = subprocess.run(cmd, capture_output=True, text=True)
             if res.returncode != 0:
                 raise RuntimeError(f"hipcc failed on {src}:\n" + res.stdout + res.stderr)
             return obj
-        jobs = max(1, min(len(SOURCES), os.cpu_count() or 1))
-        with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-            objs = list(ex.map(compile_one, sources()))
-        tmp = LIB + ".tmp"
-        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
-        res = subprocess.run(cmd, capture_output=True, text=True)
-        if res.returncode != 0:
-            raise RuntimeError("link failed:\n" + res.stdout + res.stderr)
-    os.replace(tmp, LIB)
+        jobs = [(li, src) for li in range(len(libs)) for src in sources()]
+        workers = max(1, min(len(jobs), os.cpu_count() or 1))
+        with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+            objs = list(ex.map(compile_one, jobs))
+        for li, (path, _) in enumerate(libs):
+            tmp = path + ".tmp"
+            mine = [o for (lj, _), o in zip(jobs, objs) if lj == li]
+            cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + mine
+            res = subprocess.run(cmd, capture_output=True, text=True)
+            if res.returncode != 0:
+                raise RuntimeError("link failed:\n" + res.stdout + res.stderr)
+            os.replace(tmp, path)
     return LIB
 
 

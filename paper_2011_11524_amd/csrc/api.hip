@@ -28,12 +28,18 @@ typedef unsigned __int128 u128;
 namespace {
 
 // The primes: FindPrimes(w = 64, n_min = 32, l = 2) of Section 4.5, i.e.
-// the two largest primes c*3*2^n + 1 < 2^63 with c odd and n >= 32.
-// n >= 32 makes p == 1 (mod 2^32), which the word-serial REDC relies on.
-constexpr uint64_t kP[2] = {9223371564408373249ULL, 9223371938070528001ULL};
+// the two largest primes c*3*2^n + 1 < 2^63 with c odd and n >= 32; the
+// redundant-range build takes FindPrimes(63, 32, 2), the two largest below
+// 2^62 = mu/4 (Section 8.3).  n >= 32 makes p == 1 (mod 2^32), which the
+// word-serial REDC relies on.
+constexpr uint64_t kP[2] = {kLazy ? 4611685318347718657ULL : 9223371564408373249ULL,
+                            kLazy ? 4611685692009873409ULL : 9223371938070528001ULL};
 // Smallest generators of F_p^*, and the prime factors of p - 1 that prove it.
-constexpr uint64_t kG[2] = {13, 19};
-const std::vector<uint64_t> kPm1Factors[2] = {{2, 3, 119304641ULL}, {2, 3, 5, 7, 199, 4111}};
+constexpr uint64_t kG[2] = {kLazy ? 5ULL : 13ULL, 19};
+const std::vector<uint64_t> kPm1Factors[2] = {
+    kLazy ? std::vector<uint64_t>{2, 3, 19, 41, 153151ULL} : std::vector<uint64_t>{2, 3, 119304641ULL},
+    kLazy ? std::vector<uint64_t>{2, 3, 277, 323027ULL} : std::vector<uint64_t>{2, 3, 5, 7, 199, 4111}};
+constexpr uint64_t kPrimeLimit = kLazy ? (1ULL << 62) : (1ULL << 63);
 
 uint64_t mulmod(uint64_t a, uint64_t b, uint64_t p) { return (uint64_t)((u128)a * b % p); }
 uint64_t powmod(uint64_t a, uint64_t e, uint64_t p) {
@@ -54,7 +60,7 @@ bool check_field() {
   for (int i = 0; i < 2; ++i) {
     const uint64_t p = kP[i];
     if ((p & 0xffffffffULL) != 1) return false;
-    if (p >= (1ULL << 63)) return false;
+    if (p >= kPrimeLimit) return false;
     uint64_t m = p - 1;
     for (uint64_t q : kPm1Factors[i]) {
       if (powmod(kG[i], (p - 1) / q, p) == 1) return false;
@@ -591,7 +597,7 @@ dmul_ctx* default_ctx(int device, int* rc) {
 
 extern "C" {
 
-const char* dmul_version(void) { return "dmul-gfx950 1.0"; }
+const char* dmul_version(void) { return kLazy ? "dmul-gfx950 1.1 redundant-range" : "dmul-gfx950 1.1"; }
 
 const char* dmul_strerror(int code) {
   switch (code) {

@@ -83,4 +83,49 @@ __device__ __forceinline__ uint64_t sub_lazy(uint64_t x, uint64_t y, const Prime
   return (x - y) + P.p;
 }
 
+// ---------------------------------------------------------------------------
+// Redundant ranges (Sections 8.3, 9), for primes p < 2^62 = mu/4 only: then
+// 4p < 2^64, and REDC(x, y) with x < 4p, y < p has x*y < 4p^2 < mu*p, so the
+// signed REDC value lies in (-p, p) and adding p (with no test) leaves it in
+// (0, 2p).  Butterfly values then stay below 2p (DIF) or 4p (DIT) and are
+// reduced once where they leave a transform.
+// ---------------------------------------------------------------------------
+
+// REDC(x, y) + p in (0, 2p), for x < 4p, y < p.
+__device__ __forceinline__ uint64_t mont_mul_r(uint64_t x, uint64_t y, const Prime& P) {
+  const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
+  const uint32_t y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32);
+  const uint64_t t0 = mad_u64_u32(x0, y0, 0);
+  const uint64_t t1 = mad_u64_u32(x0, y1, t0 >> 32);
+  const uint64_t t2 = mad_u64_u32(x1, y0, (uint32_t)t1);
+  const uint64_t t3 = mad_u64_u32(x1, y1, t1 >> 32);
+  unsigned c, c2;
+  const uint32_t th_lo = __builtin_addc((uint32_t)t3, (uint32_t)(t2 >> 32), 0u, &c);
+  const uint32_t th_hi = __builtin_addc((uint32_t)(t3 >> 32), 0u, c, &c2);
+  const uint32_t T0 = (uint32_t)t0, T1 = (uint32_t)t2;
+  const uint64_t h = mad_u64_u32(T0, P.p_hi, 0);
+  unsigned bw, unused;
+  const uint32_t m1 = __builtin_subc(T1, (uint32_t)h, 0u, &bw);
+  const uint32_t hh = __builtin_addc((uint32_t)(h >> 32), 0u, bw, &unused);
+  const uint64_t mp = mad_u64_u32(m1, P.p_hi, (uint64_t)hh);
+  const uint64_t th = ((uint64_t)th_hi << 32) | th_lo;
+  return th - mp + P.p;    // (th - mp) in (-p, p), as a two's-complement word
+}
+
+// x - m if x >= m, else x (one compare and select on the borrow).
+__device__ __forceinline__ uint64_t cond_sub(uint64_t x, uint64_t m) {
+  unsigned b1, b2;
+  const uint32_t d_lo = __builtin_subc((uint32_t)x, (uint32_t)m, 0u, &b1);
+  const uint32_t d_hi = __builtin_subc((uint32_t)(x >> 32), (uint32_t)(m >> 32), b1, &b2);
+  return b2 ? x : (((uint64_t)d_hi << 32) | d_lo);
+}
+
+// [0, 4p) -> [0, p)
+__device__ __forceinline__ uint64_t reduce_4p(uint64_t x, const Prime& P) {
+  return cond_sub(cond_sub(x, P.p << 1), P.p);
+}
+
+// [0, 2p) -> [0, p)
+__device__ __forceinline__ uint64_t reduce_2p(uint64_t x, const Prime& P) { return cond_sub(x, P.p); }
+
 }  // namespace dmi

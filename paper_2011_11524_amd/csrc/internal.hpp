@@ -6,8 +6,16 @@
 
 #include "field.hpp"
 
+// The redundant-range build (libdmul_lazy.so, Sections 8.3 and 9): primes
+// below 2^62 = mu/4 let butterfly values stay in [0, 2p) or [0, 4p) between
+// stages instead of being reduced to [0, p) after every operation.
+#ifndef DMUL_LAZY_FIELD
+#define DMUL_LAZY_FIELD 0
+#endif
+
 namespace dmi {
 
+constexpr bool kLazy = DMUL_LAZY_FIELD != 0;
 constexpr int kMaxLogN = 26;       // two LDS passes of at most 2^13 points each
 constexpr int kMaxLogLen = 13;     // longest sub-transform held in one workgroup's LDS
 constexpr int kMaxLogC3 = 11;      // rows of 3 * 2^logC points: logC <= 11

@@ -276,7 +276,7 @@ k_rows(Work w, Consts cs, TwiddleSet tw) {
       for (int j = 0; j < E; ++j) cur[j] = row_lds[lds_pos<LOGE>(t + j * NT)];
       if (row < R) {
 #pragma unroll
-        for (int j = 0; j < E; ++j) X[row * C + t + j * NT] = cur[j];
+        for (int j = 0; j < E; ++j) X[row * C + t + j * NT] = canonical<false>(cur[j], P);
       }
     } else {
 #pragma unroll
@@ -289,7 +289,7 @@ k_rows(Work w, Consts cs, TwiddleSet tw) {
       RL::compute(cur, roots, P, t);
       if (row < R) {
 #pragma unroll
-        for (int j = 0; j < E; ++j) X[row * C + RL::index(t, j)] = cur[j];
+        for (int j = 0; j < E; ++j) X[row * C + RL::index(t, j)] = canonical<true>(cur[j], P);
       }
     }
     round_sync<kWave>();   // the next group reuses the LDS rows
@@ -372,7 +372,7 @@ k_rows_fused(Work w, Consts cs, TwiddleSet tw) {
     RL::compute(cur, ri, P, t);
     if (in) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) X[row * C + RL::index(t, j)] = cur[j];
+      for (int j = 0; j < E; ++j) X[row * C + RL::index(t, j)] = canonical<true>(cur[j], P);
     }
     round_sync<kWave>();   // the next group reuses the LDS rows
   }
@@ -486,7 +486,7 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
     for (int q = threadIdx.x; q < (R / 2) * T; q += blockDim.x) {
       const int row = q / T, c = q % T;
       if (!tile.valid(c)) continue;
-      const uint64_t x = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
+      const uint64_t x = canonical<true>(lds[c * G::STRIDE + lds_pos<LOGE>(row)], P);
       const uint64_t y = mont_mul(lds[c * G::STRIDE + lds_pos<LOGE>(row + R / 2)], troots[row], P);
       const uint32_t j = (uint32_t)tile.column(c);
       X[(uint32_t)row * (uint32_t)C + j] = add_mod(x, y, P);
@@ -498,7 +498,8 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
     for (int q = threadIdx.x; q < R * T; q += blockDim.x) {
       const int row = q / T, c = q % T;
       if (tile.valid(c))
-        X[(uint32_t)row * (uint32_t)C + (uint32_t)tile.column(c)] = lds[c * G::STRIDE + lds_pos<LOGE>(row)];
+        X[(uint32_t)row * (uint32_t)C + (uint32_t)tile.column(c)] =
+            canonical<true>(lds[c * G::STRIDE + lds_pos<LOGE>(row)], P);
     }
   }
 }

@@ -50,8 +50,18 @@ struct Round {
   }
 
   // The butterflies of the round on the thread's registers.
+  // Canonical ranges: every value in [0, p) before and after each stage.
+  // Redundant ranges (kLazy, p < 2^62): a DIF takes values in [0, 2p) and
+  // keeps them there; a DIT takes values in [0, 4p) (canonical at its first
+  // stage), reduces the upper point of each pair to [0, 2p) and leaves its
+  // outputs in [0, 4p) (Harvey's butterflies, the p < mu/4 ranges of
+  // Section 8.3).
   static __device__ __forceinline__ void compute(uint64_t (&v)[G::E], const uint64_t* __restrict__ tw,
                                                  const Prime& P, int t) {
+    if constexpr (kLazy) {
+      compute_lazy(v, tw, P, t);
+      return;
+    }
     constexpr int E = G::E;
 #pragma unroll
     for (int s = 0; s < NB; ++s) {
@@ -84,6 +94,47 @@ struct Round {
     }
   }
 
+  static __device__ __forceinline__ void compute_lazy(uint64_t (&v)[G::E], const uint64_t* __restrict__ tw,
+                                                      const Prime& P, int t) {
+    constexpr int E = G::E;
+    const uint64_t p2 = P.p << 1;
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      const int lb = DIT ? s : (NB - 1 - s);
+      const int b = LO_B + lb;
+#pragma unroll
+      for (int j0 = 0; j0 < E; ++j0) {
+        if (j0 & (1 << lb)) continue;
+        const int j1 = j0 | (1 << lb);
+        const uint64_t x = v[j0], y = v[j1];
+        if (b == 0) {
+          if (DIT) {                            // the first DIT stage: canonical inputs
+            v[j0] = x + y;                      // [0, 2p)
+            v[j1] = x - y + P.p;                // (0, 2p)
+          } else {                              // [0, 2p) in and out
+            v[j0] = cond_sub(x + y, p2);
+            v[j1] = cond_sub(x - y + p2, p2);
+          }
+          continue;
+        }
+        const int jg = j0 >> NB, jl = j0 & ((1 << NB) - 1);
+        const int F = t + jg * G::NT;
+        const int lowF = F & ((1 << LO_B) - 1);
+        const int e = (lowF | ((jl & ((1 << lb) - 1)) << LO_B)) << (LOGL - 1 - b);
+        const uint64_t w = tw[e];
+        if (DIT) {                              // [0, 4p) in and out
+          const uint64_t xr = cond_sub(x, p2);  // [0, 2p)
+          const uint64_t u = mont_mul_r(y, w, P);   // (0, 2p)
+          v[j0] = xr + u;
+          v[j1] = xr - u + p2;
+        } else {                                // [0, 2p) in and out
+          v[j0] = cond_sub(x + y, p2);
+          v[j1] = mont_mul_r(x - y + p2, w, P);
+        }
+      }
+    }
+  }
+
   static __device__ __forceinline__ void run(uint64_t* lds, const uint64_t* __restrict__ tw,
                                              const Prime& P, int t) {
     uint64_t v[G::E];
@@ -92,6 +143,14 @@ struct Round {
     store(lds, v, t);
   }
 };
+
+// A transform's output in canonical range: DIF outputs lie in [0, 2p), DIT
+// outputs in [0, 4p) with redundant ranges; unchanged otherwise.
+template <bool DIT>
+__device__ __forceinline__ uint64_t canonical(uint64_t x, const Prime& P) {
+  if constexpr (!kLazy) return x;
+  else return DIT ? reduce_4p(x, P) : reduce_2p(x, P);
+}
 
 // Synchronisation between the rounds of in-LDS transforms.  When every
 // transform is owned by threads of one wavefront (NT <= 64, a power of two,

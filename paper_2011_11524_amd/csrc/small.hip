@@ -105,7 +105,7 @@ k_small(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g, Rec
       const int o = lds_pos<LOGE>(q);
       uint64_t x[F];
 #pragma unroll
-      for (int s = 0; s < F; ++s) x[s] = X[s * S + o];
+      for (int s = 0; s < F; ++s) x[s] = canonical<true>(X[s * S + o], P);
       if constexpr (R3) {
         const uint64_t* w3 = tw.r3_inv[pi] + r3_table_offset(LOGM);
         x[1] = mont_mul(x[1], w3[q], P);

@@ -91,3 +91,21 @@ def test_plan_forced_k_and_ranges():
     assert (p.N, p.log2_rows, p.log2_cols) == (3 << 23, 12, 11)
     assert dm.plan(na + 1000, na + 1000).N == 1 << 25
     assert dm.workspace_bytes(0, 5) == 0
+
+
+def test_redundant_range_build_exports_and_plans():
+    """libdmul_lazy.so: every declared function, its primes (the two largest
+    c*3*2^n + 1 below 2^62 with n >= 32, the oracle's FindPrimes(63, 32, 2))
+    and the planner's k rule under their product."""
+    L = dm.lib("lazy")
+    for n in _header_functions():
+        assert hasattr(L, n), f"{n} not exported by the redundant-range build"
+    p, g = dm.primes("lazy")
+    assert p == oracle.find_primes(63, 32, 2)
+    assert all(q < 2 ** 62 and q % 2 ** 32 == 1 for q in p)
+    assert g == [oracle.generator(p[0]), oracle.generator(p[1])]
+    P = p[0] * p[1]
+    for na, nb in SIZES:
+        k = next(k for k in range(18, 12, -1)
+                 if (10 ** k - 1) ** 2 * min(-(-19 * na // k), -(-19 * nb // k)) < P)
+        assert dm.plan(na, nb, variant="lazy").k == k
