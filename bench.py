@@ -214,7 +214,7 @@ def run_batched(dm, torch, steps: int, warmup: int, count: int, oracle_budget_s:
     lens = [dm.plan(len(a), len(b)).N for a, b in host]
     new_outs = lambda: [torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda") for a, b in host]
     outs = {m: new_outs() for m in ("per_product", "batched", "batched_graph", "latency_per_product",
-                                    "latency_batched")}
+                                    "latency_batched", "batched_untuned")}
     ctx = dm.Context(0, stream=torch.cuda.Stream())
     gctx = dm.Context(0, stream=torch.cuda.Stream())
     statuses = []
@@ -263,6 +263,28 @@ def run_batched(dm, torch, steps: int, warmup: int, count: int, oracle_budget_s:
         res[name]["p50_ms"] = _pct(lat, 50) if ok else None
         res[name]["p99_ms"] = _pct(lat, 99) if ok else None
         res[name]["max_ms"] = max(lat) if ok else None
+    # the same eager batch on a context without the tuned size-class table
+    old_tt = os.environ.get("DMUL_TUNE_TABLE")
+    os.environ["DMUL_TUNE_TABLE"] = ""
+    uctx = dm.Context(0, stream=torch.cuda.Stream())
+    if old_tt is None:
+        del os.environ["DMUL_TUNE_TABLE"]
+    else:
+        os.environ["DMUL_TUNE_TABLE"] = old_tt
+    upb = uctx.prepare_batch(pairs, outs["batched_untuned"])
+    ufn = batched(uctx, upb, False)
+    for _ in range(warmup):
+        ufn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ufn()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    res["batched_untuned"] = {"ms_per_batch": dt * 1e3, "digits_per_s": digits / dt,
+                              "table": "none (default row loop 1, default kernel-path rule, 8 side streams)"}
+    res["tuned_table_speedup"] = res["batched_untuned"]["ms_per_batch"] / res["batched"]["ms_per_batch"]
+    uctx.close()
     res["latency_mode"] = ("completion events on the launch streams: eager batch with its classes "
                            "on concurrent side streams, and one launch set per product on one stream")
     res["speedup"] = res["per_product"]["ms_per_batch"] / res["batched"]["ms_per_batch"]

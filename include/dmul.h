@@ -312,10 +312,22 @@ int dmul_batch_ex(dmul_ctx* ctx, size_t count, const uint64_t* const* a, const s
  * (2^e or 3 * 2^e), every workgroup of the row pass loops over `row_iters`
  * groups of rows (0 = the default).  Contexts start from the table written
  * by the project's autotuner (dmul_tune.txt beside the library, or the file
- * named by DMUL_TUNE_TABLE: lines "transform_len row_iters").  Returns
- * DMUL_OK or DMUL_EINVAL (a length that is not a supported size class, or
- * row_iters outside 0..64). */
+ * named by DMUL_TUNE_TABLE; an empty name means no table: lines
+ * "transform_len row_iters [path]" and "streams S").  Returns DMUL_OK or
+ * DMUL_EINVAL (a length that is not a supported size class, or row_iters
+ * outside 0..64). */
 int dmul_ctx_tune(dmul_ctx* ctx, uint64_t transform_len, int row_iters);
+/* Kernel path of products of transform length transform_len: 0 the
+ * default rule (the whole-product kernel up to N = 4096 for launches of 8
+ * or more products of that length, up to N = 2048 otherwise), 1 always the
+ * whole-product kernel (N <= 4096 only), 2 always the pass kernels.  Table
+ * lines "transform_len row_iters path" set it too.  Returns DMUL_OK or
+ * DMUL_EINVAL. */
+int dmul_ctx_tune_path(dmul_ctx* ctx, uint64_t transform_len, int path);
+/* Number of side streams (1..16; 0 = the default 8) over which a batch's
+ * transform-length classes run concurrently; the table line "streams S"
+ * sets it too.  Returns DMUL_OK or DMUL_EINVAL. */
+int dmul_ctx_tune_streams(dmul_ctx* ctx, int streams);
 
 /* Library version string. */
 const char* dmul_version(void);

@@ -45,7 +45,7 @@ EXPORTS = ("dmul", "dmul_ctx_create", "dmul_ctx_destroy", "dmul_ctx_set_stream",
            "dmul_ctx_profile_read", "dmul_phase_name", "dmul_ctx_profile_events", "dmul_ctx_tune",
            "dmul_spectrum_create", "dmul_spectrum_destroy", "dmul_spectrum_bytes", "dmul_ex_spectrum",
            "dmul_batch_ex", "dmul_ctx_timing", "dmul_ctx_timing_read", "dmul_ex_noalloc",
-           "dmul_spectrum_export", "dmul_debug_transpose")
+           "dmul_spectrum_export", "dmul_debug_transpose", "dmul_ctx_tune_path", "dmul_ctx_tune_streams")
 
 
 class DmulError(RuntimeError):
@@ -121,6 +121,8 @@ def lib(variant: str | None = None):
     L.dmul_ctx_profile_events.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     L.dmul_ctx_tune.argtypes = [vp, ctypes.c_uint64, ctypes.c_int]
+    L.dmul_ctx_tune_path.argtypes = [vp, ctypes.c_uint64, ctypes.c_int]
+    L.dmul_ctx_tune_streams.argtypes = [vp, ctypes.c_int]
     L.dmul_ctx_timing.argtypes = [vp, ctypes.c_int]
     L.dmul_ctx_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz]
     L.dmul_ctx_timing_read.restype = ctypes.c_long
@@ -397,6 +399,17 @@ class Context:
         rc = self._lib.dmul_ctx_tune(self._h, int(transform_len), int(row_iters))
         if rc:
             raise DmulError(rc, "dmul_ctx_tune")
+
+    def tune_path(self, transform_len: int, path: int) -> None:
+        """0 default rule, 1 whole-product kernel (N <= 4096), 2 pass kernels."""
+        rc = self._lib.dmul_ctx_tune_path(self._h, int(transform_len), int(path))
+        if rc:
+            raise DmulError(rc, "dmul_ctx_tune_path")
+
+    def tune_streams(self, streams: int) -> None:
+        rc = self._lib.dmul_ctx_tune_streams(self._h, int(streams))
+        if rc:
+            raise DmulError(rc, "dmul_ctx_tune_streams")
 
     # -- per-kernel timing ----------------------------------------------------
     def profile(self, enable: bool) -> None:

@@ -421,6 +421,18 @@ int row_iters_for(const dmul_ctx* ctx, const PlanDev& pl) {
   return v > 0 ? v : 1;
 }
 
+bool use_small(const dmul_ctx* ctx, const PlanDev& pl, size_t count) {
+  const int path = ctx->tune.path[pl.rad3 ? 1 : 0][pl.logN];
+  if (path == 1) return pl.N <= kSmallMaxN;
+  if (path == 2) return false;
+  return small_fits(pl, count);
+}
+
+int side_streams_for(const dmul_ctx* ctx) {
+  const int s = ctx->tune.streams;
+  return s > 0 ? (s < kMaxSideStreams ? s : kMaxSideStreams) : kDefaultSideStreams;
+}
+
 static bool overlaps(const uint64_t* x, size_t nx, const uint64_t* y, size_t ny) {
   if (!nx || !ny) return false;
   const uintptr_t a0 = (uintptr_t)x, a1 = a0 + nx * 8, b0 = (uintptr_t)y, b1 = b0 + ny * 8;
@@ -502,7 +514,7 @@ static int enqueue_one(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64
   }
   Marks* marks = ctx->prof;
   if (ctx->prof) ctx->prof->begin(ctx->stream);
-  if (!residues && !sa && !sb && small_fits(pl, 1))
+  if (!residues && !sa && !sb && use_small(ctx, pl, 1))
     return from_hip(launch_small(w, sh, ctx->cs, tw, ctx->d_div, &ctx->h_div, ctx->stream, marks));
   hipError_t e;
   if (sa || sb) {
@@ -542,9 +554,16 @@ void load_tuning(TuneTable* t) {
   while (fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
     unsigned long long n = 0;
-    int iters = 0, r3 = 0, e = 0;
-    if (sscanf(line, "%llu %d", &n, &iters) == 2 && size_class(n, &r3, &e) && iters > 0 && iters <= 64)
+    int iters = 0, path = 0, r3 = 0, e = 0, streams = 0;
+    if (sscanf(line, "streams %d", &streams) == 1) {
+      if (streams >= 1 && streams <= kMaxSideStreams) t->streams = streams;
+      continue;
+    }
+    const int got = sscanf(line, "%llu %d %d", &n, &iters, &path);
+    if (got >= 2 && size_class(n, &r3, &e) && iters > 0 && iters <= 64) {
       t->row_iters[r3][e] = iters;
+      if (got == 3 && path >= 0 && path <= 2 && (path != 1 || n <= kSmallMaxN)) t->path[r3][e] = path;
+    }
   }
   fclose(f);
 }
@@ -889,7 +908,7 @@ int dmul_ex_noalloc(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_t* b
     if (e == hipSuccess) e = launch_fill32(d.rec_sync, d.nblk + 1, kPoison, c->stream);
     if (e != hipSuccess) return from_hip(e);
   }
-  if (small_fits(pl, 1)) {
+  if (use_small(c, pl, 1)) {
     e = launch_small(w, sh, c->cs, tw, c->d_div, &c->h_div, c->stream, nullptr);
   } else {
     e = launch_fused(w, sh, c->cs, tw, c->d_div, c->stream, nullptr);
@@ -906,6 +925,26 @@ int dmul_ctx_tune(dmul_ctx* c, uint64_t transform_len, int row_iters) {
   DeviceGuard dg(c->device);
   std::lock_guard<std::mutex> lk(c->mu);
   c->tune.row_iters[r3][e] = row_iters;
+  if (c->batch) c->batch->forget_graphs(c->stream);
+  return DMUL_OK;
+}
+
+int dmul_ctx_tune_path(dmul_ctx* c, uint64_t transform_len, int path) {
+  int r3 = 0, e = 0;
+  if (!c || !size_class(transform_len, &r3, &e) || path < 0 || path > 2) return DMUL_EINVAL;
+  if (path == 1 && transform_len > kSmallMaxN) return DMUL_EINVAL;
+  DeviceGuard dg(c->device);
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->tune.path[r3][e] = path;
+  if (c->batch) c->batch->forget_graphs(c->stream);
+  return DMUL_OK;
+}
+
+int dmul_ctx_tune_streams(dmul_ctx* c, int streams) {
+  if (!c || streams < 0 || streams > kMaxSideStreams) return DMUL_EINVAL;
+  DeviceGuard dg(c->device);
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->tune.streams = streams;
   if (c->batch) c->batch->forget_graphs(c->stream);
   return DMUL_OK;
 }

@@ -273,7 +273,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
   // per-kernel events assume one stream)
   int nside = 0;
   if (fork) {
-    nside = (int)std::min<size_t>(cls.size(), kSideStreams);
+    nside = (int)std::min<size_t>(cls.size(), (size_t)side_streams_for(ctx));
     e = hipEventRecord(fork_, ctx->stream);
     for (int i = 0; i < nside && e == hipSuccess; ++i) e = hipStreamWaitEvent(side_[i], fork_, 0);
     if (e != hipSuccess) nside = 0;
@@ -289,7 +289,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       Work w{};
       w.many = descs + c.first + off;
       w.count = (uint32_t)std::min<size_t>(65535, c.n - off);
-      if (!c.spectra && small_fits(c.p0, c.n)) {
+      if (!c.spectra && use_small(ctx, c.p0, c.n)) {
         e = launch_small(w, c.sh, ctx->cs, tw, ctx->d_div, &ctx->h_div, st, marks);
         continue;
       }

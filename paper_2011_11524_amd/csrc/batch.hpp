@@ -11,6 +11,7 @@
 #include <dmul.h>
 
 #include "internal.hpp"
+#include "ctx.hpp"
 
 struct dmul_ctx;
 
@@ -48,10 +49,10 @@ class BatchEngine {
   // Side streams: the size classes of a batch are independent (own
   // workspaces, descriptors and status words), so they are dealt to these
   // streams, forked from and joined back to the context stream by events,
-  // and run concurrently instead of one after another.  Eight measured
-  // better than two or four (a class of a few short products is a chain of
-  // small, latency-bound launches).
-  static constexpr int kSideStreams = 8;
+  // and run concurrently instead of one after another.  How many are used
+  // is a tuned parameter (default 8: a class of a few short products is a
+  // chain of small, latency-bound launches).
+  static constexpr int kSideStreams = kMaxSideStreams;
   int ensure_side_streams();
   hipStream_t side_[kSideStreams] = {};
   hipEvent_t fork_ = nullptr;

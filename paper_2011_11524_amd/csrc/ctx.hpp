@@ -11,11 +11,15 @@
 namespace dmi {
 class BatchEngine;
 // Launch parameters per transform length N = 2^e ([0][e]) or 3 * 2^e
-// ([1][e]), from the size-class tuner (a text table: "N row_iters" per
-// line), or defaults.
+// ([1][e]), and for batches, from the size-class tuner (a text table: lines
+// "N row_iters [path]" and "streams S"), or defaults (0).
 struct TuneTable {
   int row_iters[2][kMaxLogN + 1] = {};
+  int path[2][kMaxLogN + 1] = {};   // 0 the default rule, 1 whole-product kernel, 2 pass kernels
+  int streams = 0;                  // side streams of a batch's classes (0: kDefaultSideStreams)
 };
+constexpr int kMaxSideStreams = 16;
+constexpr int kDefaultSideStreams = 8;
 struct PassTables {
   uint64_t scale[2] = {};     // R^2 N^-1 mod p per prime
   uint64_t* dev = nullptr;   // per prime: hi_fwd[N >> lb] lo_fwd[2^lb] hi_inv[N >> lb] lo_inv[2^lb]
@@ -203,6 +207,10 @@ int transpose_inplace(uint64_t* data, uint64_t rows, uint64_t cols, bool bitrev,
 int ensure_workspace(dmul_ctx* ctx, size_t words);
 int ensure_rec_sync(dmul_ctx* ctx, size_t words);
 int row_iters_for(const dmul_ctx* ctx, const PlanDev& pl);
+// Whether `count` products of plan pl launched together take the
+// whole-product kernel: the tuned path of their length, else small_fits.
+bool use_small(const dmul_ctx* ctx, const PlanDev& pl, size_t count);
+int side_streams_for(const dmul_ctx* ctx);
 bool size_class(uint64_t N, int* rad3, int* e);
 int from_hip(hipError_t e);
 int enqueue_product(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,

@@ -3,12 +3,17 @@
 For every transform length N (2^L or 3 * 2^(L-2), the size classes of the
 planner) with 2^min <= N <= 2^max, build a batch of products whose plans
 have that length (operands of random digits), time the batch with each
-candidate launch parameter, and write the fastest choice per class to
-dmul_tune.txt beside the library (read by every new context): lines
-"N row_iters".  The tuned parameter is the number of row groups each
-workgroup of the row pass loops over (1 = one group per workgroup, more =
-fewer, longer-lived workgroups); batches without cached spectra run the
-fused row pass, so that is the kernel the timings select for.
+candidate launch configuration, and keep the fastest:
+  * the kernel path: for N <= 4096 the whole-product kernel (one workgroup
+    per product) or the pass kernels (column, row and recovery passes over
+    the whole device); longer lengths always take the passes;
+  * on the pass kernels, the number of row groups each workgroup of the row
+    pass loops over (1 = one group per workgroup, more = fewer,
+    longer-lived workgroups).
+Then the number of side streams over which a batch's classes run
+concurrently is timed on the batched workload (4096 products, operands of
+10^3..10^6 digits).  The table goes to dmul_tune.txt beside the library
+(read by every new context): lines "N row_iters path" and "streams S".
 
     python -m paper_2011_11524_amd.tune [--min 7] [--max 21] [--out PATH]
 """
@@ -22,6 +27,8 @@ import time
 import numpy as np
 
 CANDIDATES = (1, 2, 4, 8)
+STREAMS = (2, 4, 8, 12, 16)
+SMALL_MAX_N = 4096
 
 
 def size_classes(lo_log: int, hi_log: int) -> list:
@@ -47,14 +54,17 @@ def limbs_for_class(N: int) -> int:
 
 
 def time_batch(ctx, pairs, outs, reps: int) -> float:
+    """Seconds per submission of the batch, marshalled once (so the timing
+    is the device work and the library's enqueue, not Python's)."""
     import torch
-    ctx.batch_async(pairs, outs)
+    pb = ctx.prepare_batch(pairs, outs)
+    ctx.run_prepared(pb)
     ctx.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        ctx.batch_async(pairs, outs)
-    ctx.sync()
+        ctx.run_prepared(pb)
+        ctx.sync()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / reps
 
@@ -71,6 +81,7 @@ def main(argv=None) -> int:
     ap.add_argument("--out", default=os.path.join(os.path.dirname(dm.LIB_PATH), "dmul_tune.txt"))
     args = ap.parse_args(argv)
     rng = np.random.default_rng(6006)
+    os.environ["DMUL_TUNE_TABLE"] = ""        # the tuner's context starts from the defaults
     ctx = dm.Context(0)
     rows = []
     for N in size_classes(args.min, args.max):
@@ -84,23 +95,49 @@ def main(argv=None) -> int:
             b = rng.integers(0, 10 ** 19, size=nl, dtype=np.uint64)
             pairs.append((dm.to_device(a), dm.to_device(b)))
             outs.append(torch.empty(2 * nl, dtype=torch.uint64, device="cuda"))
-        best = None
         times = {}
+        if N <= SMALL_MAX_N:
+            ctx.tune_path(N, 1)
+            times[("whole", 0)] = time_batch(ctx, pairs, outs, args.reps)
+        ctx.tune_path(N, 2)
         for it in CANDIDATES:
             ctx.tune(N, it)
-            t = time_batch(ctx, pairs, outs, args.reps)
-            times[it] = t
-            if best is None or t < times[best]:
-                best = it
+            times[("passes", it)] = time_batch(ctx, pairs, outs, args.reps)
+        best = min(times, key=times.get)
         ctx.tune(N, 0)
+        ctx.tune_path(N, 0)
         rows.append((N, best, times))
         print(f"N={N:8d} products={count:5d} " +
-              " ".join(f"iters{k}={v * 1e3:.3f}ms" for k, v in times.items()) + f" -> {best}", flush=True)
+              " ".join(f"{p}{'' if p == 'whole' else k}={v * 1e3:.3f}ms" for (p, k), v in times.items()) +
+              f" -> {best}", flush=True)
+        del pairs, outs
+    # side streams, on the batched workload with the tuned classes
+    for N, best, _ in rows:
+        ctx.tune_path(N, 1 if best[0] == "whole" else 2)
+        if best[0] == "passes":
+            ctx.tune(N, best[1])
+    import synth
+    da, db = synth.batched_lengths(4096)
+    pool = synth.OperandPool(10 ** 6, seed=4006, pool_limbs=4 * synth.limbs_for_digits(10 ** 6))
+    pairs, outs = [], []
+    for x, y in zip(da, db):
+        a, b = pool.take(int(x)), pool.take(int(y))
+        pairs.append((dm.to_device(a), dm.to_device(b)))
+        outs.append(torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda"))
+    stimes = {}
+    for sn in STREAMS:
+        ctx.tune_streams(sn)
+        stimes[sn] = time_batch(ctx, pairs, outs, args.reps)
+    streams = min(stimes, key=stimes.get)
+    print("streams: " + " ".join(f"{k}={v * 1e3:.3f}ms" for k, v in stimes.items()) + f" -> {streams}",
+          flush=True)
     ctx.close()
     with open(args.out, "w") as f:
-        f.write("# size-class table written by paper_2011_11524_amd/tune.py: N row_iters\n")
+        f.write("# size-class table written by paper_2011_11524_amd/tune.py: "
+                "N row_iters path (1 whole-product kernel, 2 pass kernels); streams S\n")
         for N, best, times in rows:
-            f.write(f"{N} {best}\n")
+            f.write(f"{N} {max(1, best[1])} {1 if best[0] == 'whole' else 2}\n")
+        f.write(f"streams {streams}\n")
     print(f"wrote {args.out}")
     return 0
 

@@ -595,3 +595,37 @@ def test_largest_power_of_two_length(dm, ctx):
     (a1, a2), (b1, b2), (z1, z2) = _mod_pm(a), _mod_pm(b), _mod_pm(got)
     assert z1 == a1 * b1 % (10 ** 19 - 1)
     assert z2 == a2 * b2 % (10 ** 19 + 1)
+
+
+def test_tuned_paths_and_streams(dm):
+    """Every kernel path a size-class table may choose (whole-product kernel
+    or passes at N <= 4096, any row-loop count) and side-stream counts from
+    1 to 16 give the oracle's products."""
+    import torch
+    _note("tuned kernel paths and side streams")
+    c = dm.Context(0, stream=torch.cuda.Stream())
+    try:
+        rng = np.random.default_rng(5150)
+        host = [(rng.integers(0, 10 ** 19, size=int(x), dtype=np.uint64),
+                 rng.integers(0, 10 ** 19, size=int(y), dtype=np.uint64))
+                for x, y in zip(10 ** rng.uniform(0.5, 3.6, 40), 10 ** rng.uniform(0.5, 3.6, 40))]
+        want = [oracle.mul_ntt(a, b) for a, b in host]
+        pairs = [(dm.to_device(a), dm.to_device(b)) for a, b in host]
+        Ns = sorted({dm.plan(len(a), len(b)).N for a, b in host})
+        for path, iters, streams in ((1, 0, 1), (2, 1, 16), (2, 4, 3), (0, 8, 0)):
+            for N in Ns:
+                c.tune_path(N, path if (path != 1 or N <= 4096) else 2)
+                c.tune(N, iters)
+            c.tune_streams(streams)
+            for graph in (False, True):
+                outs, st = c.batch(pairs, graph=graph)
+                assert st == [0] * len(pairs)
+                for o, w in zip(outs, want):
+                    np.testing.assert_array_equal(dm.to_host(o), w)
+            np.testing.assert_array_equal(dm.to_host(c.mul(*pairs[5])), want[5])
+        with pytest.raises(dm.DmulError):
+            c.tune_path(8192, 1)
+        with pytest.raises(dm.DmulError):
+            c.tune_streams(17)
+    finally:
+        c.close()
