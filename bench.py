@@ -311,6 +311,36 @@ def run_batched(dm, torch, steps: int, warmup: int, count: int, oracle_budget_s:
     return res
 
 
+def batched_only(dm, torch, steps: int, warmup: int, count: int) -> int:
+    """The eager batch alone, submitted `steps` times after `warmup` (for a
+    kernel trace of the batched workload); prints one JSON line."""
+    import synth
+    da, db = synth.batched_lengths(count)
+    pool = synth.OperandPool(10 ** 6, seed=4006, pool_limbs=4 * synth.limbs_for_digits(10 ** 6))
+    pairs, outs, digits = [], [], 0
+    for x, y in zip(da, db):
+        a, b = pool.take(int(x)), pool.take(int(y))
+        pairs.append((dm.to_device(a), dm.to_device(b)))
+        outs.append(torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda"))
+        digits += int(x) + int(y)
+    ctx = dm.Context(0, stream=torch.cuda.Stream())
+    pb = ctx.prepare_batch(pairs, outs)
+    for _ in range(warmup):
+        ctx.run_prepared(pb)
+        ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.run_prepared(pb)
+        ctx.sync()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ctx.close()
+    print(json.dumps({"workload": f"{count} batched products (eager)", "ms_per_batch": dt * 1e3,
+                      "digits_per_s": digits / dt, "steps": steps}), flush=True)
+    return 0
+
+
 def run_serving(dm, torch, count: int, seed: int = 5005, oracle_budget_s: float = 6.0):
     """The serving workload: `count` requests, each operand length
     round(10^U(2, 7)) digits, Poisson arrivals at 70% of the device's service
@@ -433,6 +463,8 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time at most")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-product batched workload")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only submit the 4096-product batch (eager) --steps times, for kernel traces")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--no-serving", action="store_true", help="skip the 100k-request serving workload")
     ap.add_argument("--requests", type=int, default=100_000)
@@ -462,6 +494,9 @@ def main() -> int:
         libbuild.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+
+    if args.batched_only:
+        return batched_only(dm, torch, args.steps, args.warmup, args.batch_count)
 
     D = args.digits
     DB = args.digits_b or D

@@ -335,39 +335,78 @@ k_rows_fused(Work w, Consts cs, TwiddleSet tw) {
 
   using R0 = typename RoundBits<LOGC, LOGE, false, 0>::type;
   using RL = typename RoundBits<LOGC, LOGE, true, NR - 1>::type;
+  // With two or more rounds, the forward DIF's last round (the low bits)
+  // and the inverse DIT's first round (bits [0, LOGE)) both act within runs
+  // of 2^LOGE consecutive points: a thread loads its run once (the DIT's
+  // first-round layout), finishes the DIF there, forms the pointwise product
+  // and runs the DIT's first round, all in registers.
+  using DL = typename RoundBits<LOGC, LOGE, false, NR - 1>::type;   // the DIF's last round
+  using D0 = typename RoundBits<LOGC, LOGE, true, 0>::type;         // the DIT's first round
+  constexpr bool kJoin = NR >= 2;
   uint64_t cur[E], xs[E];
   for (uint32_t g = blockIdx.x; g < groups; g += gridDim.x) {
     const uint64_t row = (uint64_t)g * RPW + r;
     const bool in = row < R;
-    // forward DIF of X's row: round 0 on the loaded registers, the rest in LDS
+    if constexpr (kJoin) {
+      // forward DIF of X's row: round 0 on the loaded registers, the middle
+      // rounds in LDS, the last on the thread's run of consecutive points
 #pragma unroll
-    for (int j = 0; j < E; ++j) cur[j] = in ? X[row * C + t + j * NT] : 0;
-    R0::compute(cur, rf, P, t);
-    R0::store(row_lds, cur, t);
-    round_sync<kWave>();
-    RoundRange<LOGC, LOGE, false, 1, NR, kWave>::run(row_lds, rf, P, t);
+      for (int j = 0; j < E; ++j) cur[j] = in ? X[row * C + t + j * NT] : 0;
+      R0::compute(cur, rf, P, t);
+      R0::store(row_lds, cur, t);
+      round_sync<kWave>();
+      RoundRange<LOGC, LOGE, false, 1, NR - 1, kWave>::run(row_lds, rf, P, t);
+      D0::load(row_lds, xs, t);
+      DL::compute(xs, rf, P, t);
+      if (!square) {
+        round_sync<kWave>();                     // X's run read before Y's overwrites the row
 #pragma unroll
-    for (int j = 0; j < E; ++j) xs[j] = row_lds[lds_pos<LOGE>(t + j * NT)];
-    if (square) {
+        for (int j = 0; j < E; ++j) cur[j] = in ? Y[row * C + t + j * NT] : 0;
+        R0::compute(cur, rf, P, t);
+        R0::store(row_lds, cur, t);
+        round_sync<kWave>();
+        RoundRange<LOGC, LOGE, false, 1, NR - 1, kWave>::run(row_lds, rf, P, t);
+        D0::load(row_lds, cur, t);
+        DL::compute(cur, rf, P, t);
+      }
 #pragma unroll
-      for (int j = 0; j < E; ++j) row_lds[lds_pos<LOGE>(t + j * NT)] = mont_mul(xs[j], xs[j], P);
+      for (int j = 0; j < E; ++j) cur[j] = mont_mul(xs[j], square ? xs[j] : cur[j], P);
+      D0::compute(cur, ri, P, t);
+      round_sync<kWave>();                       // every run read before the product overwrites the row
+      D0::store(row_lds, cur, t);
+      round_sync<kWave>();
+      RoundRange<LOGC, LOGE, true, 1, NR - 1, kWave>::run(row_lds, ri, P, t);
     } else {
-      round_sync<kWave>();                       // X's spectrum read before Y's overwrites the row
+      // forward DIF of X's row: round 0 on the loaded registers, the rest in LDS
 #pragma unroll
-      for (int j = 0; j < E; ++j) cur[j] = in ? Y[row * C + t + j * NT] : 0;
+      for (int j = 0; j < E; ++j) cur[j] = in ? X[row * C + t + j * NT] : 0;
       R0::compute(cur, rf, P, t);
       R0::store(row_lds, cur, t);
       round_sync<kWave>();
       RoundRange<LOGC, LOGE, false, 1, NR, kWave>::run(row_lds, rf, P, t);
 #pragma unroll
-      for (int j = 0; j < E; ++j) {
-        const int o = lds_pos<LOGE>(t + j * NT);
-        row_lds[o] = mont_mul(xs[j], row_lds[o], P);
+      for (int j = 0; j < E; ++j) xs[j] = row_lds[lds_pos<LOGE>(t + j * NT)];
+      if (square) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) row_lds[lds_pos<LOGE>(t + j * NT)] = mont_mul(xs[j], xs[j], P);
+      } else {
+        round_sync<kWave>();                     // X's spectrum read before Y's overwrites the row
+#pragma unroll
+        for (int j = 0; j < E; ++j) cur[j] = in ? Y[row * C + t + j * NT] : 0;
+        R0::compute(cur, rf, P, t);
+        R0::store(row_lds, cur, t);
+        round_sync<kWave>();
+        RoundRange<LOGC, LOGE, false, 1, NR, kWave>::run(row_lds, rf, P, t);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          const int o = lds_pos<LOGE>(t + j * NT);
+          row_lds[o] = mont_mul(xs[j], row_lds[o], P);
+        }
       }
+      round_sync<kWave>();
+      // inverse DIT: all rounds but the last in LDS, the last ends in registers
+      RoundRange<LOGC, LOGE, true, 0, NR - 1, kWave>::run(row_lds, ri, P, t);
     }
-    round_sync<kWave>();
-    // inverse DIT: all rounds but the last in LDS, the last ends in registers
-    RoundRange<LOGC, LOGE, true, 0, NR - 1, kWave>::run(row_lds, ri, P, t);
     RL::load(row_lds, cur, t);
     RL::compute(cur, ri, P, t);
     if (in) {
