@@ -145,7 +145,8 @@ int dmul_ex(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size
  * device -- on two streams or two contexts of that device, without a
  * dmul_sync or stream ordering between them -- race and give wrong
  * products.  Profiling and completion timing do not record these
- * products. */
+ * products.  DMUL_EDEVICE if the runtime could not give the array's address
+ * when the context was made. */
 int dmul_ex_noalloc(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b, size_t nb,
                     uint64_t* out, unsigned flags);
 

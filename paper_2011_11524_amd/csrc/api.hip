@@ -737,7 +737,9 @@ int dmul_ctx_create(dmul_ctx** out, int device, size_t budget) {
   if (e != hipSuccess) rc = from_hip(e);
   if (!rc) rc = ensure_status(c, 1);
   if (!rc) rc = prebuild_pass_tables(c);
-  if (!rc) rc = scratch_address(device, &c->scratch);
+  // without the static array's address only dmul_ex_noalloc is unavailable
+  // (it then returns DMUL_EDEVICE); every other entry point works
+  if (!rc && scratch_address(device, &c->scratch) != DMUL_OK) c->scratch = nullptr;
 
   if (rc) {
     dmul_ctx_destroy(c);
