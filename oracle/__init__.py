@@ -20,6 +20,9 @@ Contents
   tests check one by one.
 * ``lambda_digits`` -- eq. lambda of Section 4.2 in exact integer arithmetic
   (pure Python; a handful of calls).
+* ``sanitize_check.c`` -- a driver that runs every entry point of oracle.c
+  under AddressSanitizer and UndefinedBehaviorSanitizer (built by the test
+  suite with gcc).
 """
 from __future__ import annotations
 
