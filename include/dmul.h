@@ -113,9 +113,27 @@ typedef struct dmul_plan_info {
 int dmul(const uint64_t* a, size_t na, const uint64_t* b, size_t nb, uint64_t* out);
 
 /* Context on `device` with a workspace budget in bytes (0 = no limit).
- * Returns DMUL_OK and *ctx, or DMUL_EDEVICE / DMUL_ENOMEM.  Every call on
- * a context (or a spectrum) works on the context's device and leaves the
- * calling thread's current HIP device as it found it. */
+ * Returns DMUL_OK and *ctx, or DMUL_EDEVICE / DMUL_ENOMEM / DMUL_EINVAL.
+ * Every call on a context (or a spectrum) works on the context's device and leaves the
+ * calling thread's current HIP device as it found it.
+ *
+ * Environment, read here once per context (the default contexts of dmul
+ * and dmul_host included):
+ *   DMUL_HBM_BUDGET=<bytes>  the budget when hbm_budget_bytes is 0 (0 = no
+ *       limit);
+ *   DMUL_FORCE_K=<k>, 13 <= k <= 18: the group size k (Section 3.1) of
+ *       every product of the context whose flags leave k to the library
+ *       (dmul_debug_residues excepted),
+ *       as if they held DMUL_FLAG_FORCE_K(k) (a product beyond the bound
+ *       of eq. ci_bound then fails with DMUL_ERANGE); flags naming a k win;
+ *   DMUL_POISON (set, and not "0"): fill the scratch of every product
+ *       with 0xff first;
+ *   DMUL_TUNE_TABLE  see dmul_ctx_tune.
+ * An unset or empty DMUL_HBM_BUDGET or DMUL_FORCE_K is ignored; any other
+ * value that is not a whole decimal number in its range makes this call
+ * fail with DMUL_EINVAL.
+ * dmul_plan, dmul_workspace_bytes and dmul_spectrum_bytes take no context
+ * and read none of them. */
 int dmul_ctx_create(dmul_ctx** ctx, int device, size_t hbm_budget_bytes);
 /* Waits for the context's work, then frees everything it owns. */
 int dmul_ctx_destroy(dmul_ctx* ctx);
@@ -192,8 +210,9 @@ void dmul_primes(uint64_t p[2], uint64_t g[2]);
 
 /* Debug view of the convolution step alone: writes res[0..N) and
  * res[N..2N) = the cyclic convolution of the digit groups of a and b modulo
- * p1 and modulo p2 (device pointer `res` of 2N words, N from dmul_plan),
- * blocking.  For tests of the transform separately from answer recovery. */
+ * p1 and modulo p2 (device pointer `res` of 2N words, N from dmul_plan
+ * with the same flags: DMUL_FORCE_K does not apply here), blocking.  For
+ * tests of the transform separately from answer recovery. */
 int dmul_debug_residues(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64_t* b,
                         size_t nb, uint64_t* res, unsigned flags);
 

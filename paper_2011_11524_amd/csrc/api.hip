@@ -602,6 +602,27 @@ int scratch_address(int device, uint64_t** out) {
 std::mutex g_default_mu;
 std::map<int, dmul_ctx*> g_default;
 
+// A whole decimal number in [lo, hi] from the environment variable `name`:
+// 1 with *v set, 0 when it is unset or empty, -1 when it is anything else.
+int env_number(const char* name, unsigned long long lo, unsigned long long hi, unsigned long long* v) {
+  const char* s = getenv(name);
+  if (!s || !*s) return 0;
+  unsigned long long x = 0;
+  for (const char* q = s; *q; ++q) {
+    if (*q < '0' || *q > '9' || x > (~0ULL - 9) / 10) return -1;
+    x = 10 * x + (unsigned)(*q - '0');
+  }
+  if (x < lo || x > hi) return -1;
+  *v = x;
+  return 1;
+}
+
+// The flags a product of context c runs with: DMUL_FORCE_K fills in k
+// where the caller's flags leave it to the library.
+unsigned with_env_k(const dmul_ctx* c, unsigned flags) {
+  return (flags & DMUL_FLAG_K_MASK) ? flags : (flags | c->env_k);
+}
+
 dmul_ctx* default_ctx(int device, int* rc) {
   std::lock_guard<std::mutex> lk(g_default_mu);
   auto it = g_default.find(device);
@@ -663,6 +684,11 @@ size_t dmul_workspace_bytes(size_t na, size_t nb) {
 int dmul_ctx_create(dmul_ctx** out, int device, size_t budget) {
   if (!out) return DMUL_EINVAL;
   *out = nullptr;
+  // DMUL_HBM_BUDGET (bytes, 0 = no limit) stands in for a budget argument of 0;
+  // DMUL_FORCE_K (kMinK..18) for the k field of flags that leave it 0
+  unsigned long long env_budget = 0, env_k = 0;
+  if (env_number("DMUL_HBM_BUDGET", 0, ~0ULL, &env_budget) < 0) return DMUL_EINVAL;
+  if (env_number("DMUL_FORCE_K", kMinK, 18, &env_k) < 0) return DMUL_EINVAL;
   if (!check_field()) return DMUL_EDEVICE;
   const DivTable dt = make_div_table();
   if (!check_div_table(dt)) return DMUL_EDEVICE;
@@ -672,7 +698,8 @@ int dmul_ctx_create(dmul_ctx** out, int device, size_t budget) {
   dmul_ctx* c = new (std::nothrow) dmul_ctx;
   if (!c) return DMUL_ENOMEM;
   c->device = device;
-  c->budget = budget;
+  c->budget = budget ? budget : (size_t)env_budget;
+  c->env_k = (unsigned)env_k;
   if (const char* pv = getenv("DMUL_POISON")) c->poison = pv[0] && strcmp(pv, "0") != 0;
   c->h_div = dt;
   load_tuning(&c->tune);
@@ -790,7 +817,7 @@ int dmul_ex(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_t* b, size_t
   DeviceGuard dg(c->device);
   if (!dg.ok()) return DMUL_EDEVICE;
   std::lock_guard<std::mutex> lk(c->mu);
-  rc = enqueue_product(c, a, na, b, nb, out, flags, c->d_status, nullptr);
+  rc = enqueue_product(c, a, na, b, nb, out, with_env_k(c, flags), c->d_status, nullptr);
   if (rc == DMUL_EDEVICE && c->pending == DMUL_OK) c->pending = rc;
   return rc;
 }
@@ -870,6 +897,7 @@ int dmul_debug_residues(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_
   int rc;
   {
     std::lock_guard<std::mutex> lk(c->mu);
+    // flags as given: the caller sized res from dmul_plan with the same flags
     rc = enqueue_product(c, a, na, b, nb, nullptr, flags, c->d_status, res);
   }
   const int rs = dmul_sync(c);
@@ -886,7 +914,7 @@ int dmul_ex_noalloc(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_t* b
   std::lock_guard<std::mutex> lk(c->mu);
   if (na == 0 || nb == 0) return from_hip(launch_zero(out, na + nb, c->stream));
   PlanDev pl;
-  rc = make_plan(na, nb, flags, &pl);
+  rc = make_plan(na, nb, with_env_k(c, flags), &pl);
   if (rc) return rc;
   if (pl.N > kStaticMaxN) return DMUL_ENOMEM;      // beyond the static scratch
   TwiddleSet tw;
@@ -1049,7 +1077,7 @@ int dmul_batch_ex(dmul_ctx* c, size_t count, const uint64_t* const* a, const siz
   }
   c->status_used = off + count;
   for (size_t i = 0; i < count; ++i) status[i] = DMUL_OK;
-  rc = c->batch->run(c, count, a, na, sa, b, nb, sb, out, status, flags, c->d_status + off);
+  rc = c->batch->run(c, count, a, na, sa, b, nb, sb, out, status, with_env_k(c, flags), c->d_status + off);
   if (rc == DMUL_EDEVICE && c->pending == DMUL_OK) c->pending = rc;
   return rc;
 }
@@ -1071,6 +1099,7 @@ int dmul_spectrum_create(dmul_ctx* c, const uint64_t* a, size_t na, size_t nb, u
   if (!c || !out) return DMUL_EINVAL;
   *out = nullptr;
   if (!a || na == 0 || nb == 0) return DMUL_EINVAL;
+  flags = with_env_k(c, flags);
   PlanDev pl;
   int rc = make_plan(na, nb, flags, &pl);
   if (rc) return rc;
@@ -1167,7 +1196,7 @@ int dmul_ex_spectrum(dmul_ctx* c, const dmul_spectrum* sa, const uint64_t* b, si
   DeviceGuard dg(c->device);
   if (!dg.ok()) return DMUL_EDEVICE;
   std::lock_guard<std::mutex> lk(c->mu);
-  const int rc = enqueue_product(c, nullptr, sa->na, b, nb, out, flags, c->d_status, nullptr, sa, sb);
+  const int rc = enqueue_product(c, nullptr, sa->na, b, nb, out, with_env_k(c, flags), c->d_status, nullptr, sa, sb);
   if (rc == DMUL_EDEVICE && c->pending == DMUL_OK) c->pending = rc;
   return rc;
 }

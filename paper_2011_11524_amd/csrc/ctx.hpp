@@ -151,6 +151,7 @@ struct dmul_ctx {
   size_t rec_sync_cap = 0;
   dmi::TuneTable tune;                  // per transform length launch parameters
   bool poison = false;                  // DMUL_POISON: fill scratch with 0xff before every product
+  unsigned env_k = 0;                   // DMUL_FORCE_K: k of products whose flags name none (0: choose)
   std::mutex mu;
 };
 

@@ -109,3 +109,17 @@ def test_redundant_range_build_exports_and_plans():
         k = next(k for k in range(18, 12, -1)
                  if (10 ** k - 1) ** 2 * min(-(-19 * na // k), -(-19 * nb // k)) < P)
         assert dm.plan(na, nb, variant="lazy").k == k
+
+
+@pytest.mark.parametrize("name,value", [("DMUL_FORCE_K", "12"), ("DMUL_FORCE_K", "19"),
+                                        ("DMUL_FORCE_K", "k15"), ("DMUL_FORCE_K", "15 "),
+                                        ("DMUL_HBM_BUDGET", "-1"), ("DMUL_HBM_BUDGET", "1e9"),
+                                        ("DMUL_HBM_BUDGET", "99999999999999999999999")])
+def test_ctx_create_rejects_bad_environment(monkeypatch, name, value):
+    """A malformed DMUL_FORCE_K or DMUL_HBM_BUDGET fails context creation
+    with DMUL_EINVAL before any device call (so this runs without a GPU)."""
+    monkeypatch.setenv(name, value)
+    L = dm.lib()
+    h = ctypes.c_void_p(1)
+    assert L.dmul_ctx_create(ctypes.byref(h), 0, 0) == dm.DMUL_EINVAL
+    assert h.value is None
