@@ -131,7 +131,7 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
         const int row = q / T, sl = q % T;       // row < R/2; v[s + PER/2] is row + R/2
         const uint64_t a = v[s], b = v[s + PER / 2];
         lds[sl * G::STRIDE + lds_pos<LOGE>(row)] = add_mod(a, b, P);
-        lds[sl * G::STRIDE + lds_pos<LOGE>(row + R / 2)] = mont_mul(sub_lazy(a, b, P), rts[row], P);
+        lds[sl * G::STRIDE + lds_pos<LOGE>(row + R / 2)] = mont_mul(sub_mod(a, b, P), rts[row], P);
       }
     } else {
 #pragma unroll
@@ -526,7 +526,8 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
       const int row = q / T, c = q % T;
       if (!tile.valid(c)) continue;
       const uint64_t x = canonical<true>(lds[c * G::STRIDE + lds_pos<LOGE>(row)], P);
-      const uint64_t y = mont_mul(lds[c * G::STRIDE + lds_pos<LOGE>(row + R / 2)], troots[row], P);
+      const uint64_t y = mont_mul(canonical<true>(lds[c * G::STRIDE + lds_pos<LOGE>(row + R / 2)], P),
+                                  troots[row], P);
       const uint32_t j = (uint32_t)tile.column(c);
       X[(uint32_t)row * (uint32_t)C + j] = add_mod(x, y, P);
       X[(uint32_t)(row + R / 2) * (uint32_t)C + j] = sub_mod(x, y, P);

@@ -88,7 +88,7 @@ struct Round {
           v[j1] = sub_mod(x, u, P);
         } else {
           v[j0] = add_mod(x, y, P);
-          v[j1] = mont_mul(sub_lazy(x, y, P), w, P);
+          v[j1] = mont_mul(sub_mod(x, y, P), w, P);
         }
       }
     }
@@ -335,7 +335,7 @@ __device__ __forceinline__ void dft3(uint64_t& a, uint64_t& b, uint64_t& c, uint
                                      const Prime& P) {
   const uint64_t bc = add_mod(b, c, P);
   const uint64_t m = sub_mod(a, half_mod(bc, P), P);
-  const uint64_t v = mont_mul(sub_lazy(b, c, P), kappa, P);
+  const uint64_t v = mont_mul(sub_mod(b, c, P), kappa, P);
   a = add_mod(a, bc, P);
   b = add_mod(m, v, P);
   c = sub_mod(m, v, P);
