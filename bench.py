@@ -40,18 +40,19 @@ HBM_PEAK_GBS = 8000.0
 
 # Word-level operation counts of the field arithmetic (32-bit VALU ops),
 # from the formulas the kernels implement: a Montgomery product is six
-# 32x32->64 multiply-adds plus fourteen adds, negations, carries and the
-# final conditional subtraction; a modular add or subtract is a 64-bit
-# add/sub (2), compare (1), 64-bit correction (2), select (2).
-OPS_MODMUL = 20
+# 32x32->64 multiply-adds (the middle partial products chained through the
+# 64-bit addend, operands below 2^63) plus ten moves, subtractions with
+# borrow, selects and adds (the reduction's borrow and the conditional +p);
+# a modular add or subtract is a 64-bit add/sub (2), compare (1), 64-bit
+# correction (2), select (2).
+OPS_MODMUL = 16
 OPS_MODADD = 7
-OPS_LAZYSUB = 3
-OPS_DIF = OPS_MODADD + OPS_LAZYSUB + OPS_MODMUL     # x+y, (x-y+p)*w
+OPS_DIF = 2 * OPS_MODADD + OPS_MODMUL              # x+y, (x-y mod p)*w
 OPS_DIT = OPS_MODMUL + 2 * OPS_MODADD              # u = y*w, x+u, x-u
 OPS_BF1 = 2 * OPS_MODADD                           # factor 1: x+y, x-y
 # radix-3 butterfly of a row of 3M points, per triple: b+c, a+(b+c), a halving
-# (5), a-(b+c)/2, b-c+p, kappa*(b-c), m+v, m-v, and the two twiddle products
-OPS_R3 = 5 * OPS_MODADD + 5 + OPS_LAZYSUB + 3 * OPS_MODMUL
+# (5), a-(b+c)/2, b-c, kappa*(b-c), m+v, m-v, and the two twiddle products
+OPS_R3 = 6 * OPS_MODADD + 5 + 3 * OPS_MODMUL
 OPS_SPLIT = 24      # two multiply-high divisions by powers of ten per group
 OPS_CRT = 120       # CRT modmul, 64x64 product, four 2-by-1 divisions
 OPS_CARRY = 12      # per position: carry map, scan step, digit
