@@ -215,7 +215,7 @@ def run_batched(dm, torch, steps: int, warmup: int, count: int, oracle_budget_s:
     lens = [dm.plan(len(a), len(b)).N for a, b in host]
     new_outs = lambda: [torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda") for a, b in host]
     outs = {m: new_outs() for m in ("per_product", "batched", "batched_graph", "latency_per_product",
-                                    "latency_batched", "batched_untuned")}
+                                    "latency_batched", "batched_untuned", "batched_queue")}
     ctx = dm.Context(0, stream=torch.cuda.Stream())
     gctx = dm.Context(0, stream=torch.cuda.Stream())
     statuses = []
@@ -286,6 +286,23 @@ def run_batched(dm, torch, steps: int, warmup: int, count: int, oracle_budget_s:
                               "table": "none (default row loop 1, default kernel-path rule, 8 side streams)"}
     res["tuned_table_speedup"] = res["batched_untuned"]["ms_per_batch"] / res["batched"]["ms_per_batch"]
     uctx.close()
+    # the same eager batch with the whole-product classes in persistent
+    # queue launches (one per tier of lengths) instead of one per length
+    qctx = dm.Context(0, stream=torch.cuda.Stream())
+    qctx.tune_queue(True)
+    qfn = batched(qctx, qctx.prepare_batch(pairs, outs["batched_queue"]), False)
+    for _ in range(warmup):
+        qfn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        qfn()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    res["batched_queue"] = {"ms_per_batch": dt * 1e3, "digits_per_s": digits / dt,
+                            "whole_product_launches": "persistent, one queue per tier of lengths"}
+    res["queue_vs_per_length"] = res["batched"]["ms_per_batch"] / res["batched_queue"]["ms_per_batch"]
+    qctx.close()
     res["latency_mode"] = ("completion events on the launch streams: eager batch with its classes "
                            "on concurrent side streams, and one launch set per product on one stream")
     res["speedup"] = res["per_product"]["ms_per_batch"] / res["batched"]["ms_per_batch"]

@@ -348,6 +348,16 @@ int dmul_ctx_tune_path(dmul_ctx* ctx, uint64_t transform_len, int path);
  * transform-length classes run concurrently; the table line "streams S"
  * sets it too.  Returns DMUL_OK or DMUL_EINVAL. */
 int dmul_ctx_tune_streams(dmul_ctx* ctx, int streams);
+/* Persistent whole-product launches in batches: with queue = 1 (table
+ * line "queue Q"), the classes of a batch that take the whole-product
+ * kernel are not launched one per transform length but gathered into at
+ * most three launches by register and LDS need (sub-transforms of up to
+ * 2^8 points, 2^9..2^10, longer), each a grid of as many workgroups as the
+ * device holds at once that take the products, longest first, from a queue
+ * in device memory; with 0 (the default), one launch per length with one
+ * workgroup per product.  Results are identical.  Returns DMUL_OK or
+ * DMUL_EINVAL. */
+int dmul_ctx_tune_queue(dmul_ctx* ctx, int queue);
 
 /* Library version string. */
 const char* dmul_version(void);

@@ -45,7 +45,8 @@ EXPORTS = ("dmul", "dmul_ctx_create", "dmul_ctx_destroy", "dmul_ctx_set_stream",
            "dmul_ctx_profile_read", "dmul_phase_name", "dmul_ctx_profile_events", "dmul_ctx_tune",
            "dmul_spectrum_create", "dmul_spectrum_destroy", "dmul_spectrum_bytes", "dmul_ex_spectrum",
            "dmul_batch_ex", "dmul_ctx_timing", "dmul_ctx_timing_read", "dmul_ex_noalloc",
-           "dmul_spectrum_export", "dmul_debug_transpose", "dmul_ctx_tune_path", "dmul_ctx_tune_streams")
+           "dmul_spectrum_export", "dmul_debug_transpose", "dmul_ctx_tune_path", "dmul_ctx_tune_streams",
+           "dmul_ctx_tune_queue")
 
 
 class DmulError(RuntimeError):
@@ -123,6 +124,7 @@ def lib(variant: str | None = None):
     L.dmul_ctx_tune.argtypes = [vp, ctypes.c_uint64, ctypes.c_int]
     L.dmul_ctx_tune_path.argtypes = [vp, ctypes.c_uint64, ctypes.c_int]
     L.dmul_ctx_tune_streams.argtypes = [vp, ctypes.c_int]
+    L.dmul_ctx_tune_queue.argtypes = [vp, ctypes.c_int]
     L.dmul_ctx_timing.argtypes = [vp, ctypes.c_int]
     L.dmul_ctx_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz]
     L.dmul_ctx_timing_read.restype = ctypes.c_long
@@ -410,6 +412,13 @@ class Context:
         rc = self._lib.dmul_ctx_tune_streams(self._h, int(streams))
         if rc:
             raise DmulError(rc, "dmul_ctx_tune_streams")
+
+    def tune_queue(self, on: bool) -> None:
+        """Whole-product classes of a batch in persistent launches per tier
+        (True, the default) or one launch per transform length (False)."""
+        rc = self._lib.dmul_ctx_tune_queue(self._h, 1 if on else 0)
+        if rc:
+            raise DmulError(rc, "dmul_ctx_tune_queue")
 
     # -- per-kernel timing ----------------------------------------------------
     def profile(self, enable: bool) -> None:

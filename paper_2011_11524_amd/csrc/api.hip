@@ -559,6 +559,11 @@ void load_tuning(TuneTable* t) {
       if (streams >= 1 && streams <= kMaxSideStreams) t->streams = streams;
       continue;
     }
+    int queue = 0;
+    if (sscanf(line, "queue %d", &queue) == 1) {
+      if (queue == 0 || queue == 1) t->queue = queue;
+      continue;
+    }
     const int got = sscanf(line, "%llu %d %d", &n, &iters, &path);
     if (got >= 2 && size_class(n, &r3, &e) && iters > 0 && iters <= 64) {
       t->row_iters[r3][e] = iters;
@@ -975,6 +980,15 @@ int dmul_ctx_tune_streams(dmul_ctx* c, int streams) {
   DeviceGuard dg(c->device);
   std::lock_guard<std::mutex> lk(c->mu);
   c->tune.streams = streams;
+  if (c->batch) c->batch->forget_graphs(c->stream);
+  return DMUL_OK;
+}
+
+int dmul_ctx_tune_queue(dmul_ctx* c, int queue) {
+  if (!c || (queue != 0 && queue != 1)) return DMUL_EINVAL;
+  DeviceGuard dg(c->device);
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->tune.queue = queue;
   if (c->batch) c->batch->forget_graphs(c->stream);
   return DMUL_OK;
 }

@@ -185,6 +185,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
     ++nvalid;
   }
   if (nvalid == 0) return DMUL_OK;
+  sync_words += kQueueTiers;          // the queue heads of the persistent launches
   int rc = reserve(ctx, ws_words, sync_words, nvalid);
   if (rc) {
     for (auto& kv : classes)
@@ -194,18 +195,36 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
   // the staging buffer may still feed the previous batch's copy
   if (hipEventSynchronize(copied_) != hipSuccess) return DMUL_EDEVICE;
   size_t wofs = 0, sofs = 0, di = 0;
-  struct Cls { PlanDev p0; int spectra; size_t first, n; Shape sh; const std::vector<uint32_t>* idx; };
+  // tier >= 0: the class takes the whole-product kernel through the
+  // persistent launch of its tier
+  struct Cls { PlanDev p0; int spectra; size_t first, n; Shape sh; const std::vector<uint32_t>* idx; int tier; };
   std::vector<Cls> cls;
   for (auto& kv : classes) {
     const PlanDev& p0 = plans[kv.second[0]];
-    Cls c{p0, kv.first.second, di, kv.second.size(), {}, &kv.second};
+    Cls c{p0, kv.first.second, 0, kv.second.size(), {}, &kv.second, -1};
+    if (ctx->tune.queue && !c.spectra && use_small(ctx, p0, c.n)) c.tier = small_tier(p0);
+    cls.push_back(c);
+  }
+  // queued classes first, tier by tier, longest first (the order in which
+  // a tier's queue hands out its products); then the others
+  std::stable_sort(cls.begin(), cls.end(), [](const Cls& x, const Cls& y) {
+    const int tx = x.tier < 0 ? kQueueTiers : x.tier, ty = y.tier < 0 ? kQueueTiers : y.tier;
+    if (tx != ty) return tx < ty;
+    return x.tier >= 0 && x.p0.N > y.p0.N;
+  });
+  for (Cls& c : cls) {
+    const PlanDev& p0 = c.p0;
+    TwiddleSet ctw;                   // tables exist before any capture
+    rc = get_twiddles(ctx, p0, &ctw);
+    if (rc) return rc;
+    c.first = di;
     c.sh.logR = p0.logR;
     c.sh.logC = p0.logC;
     c.sh.rad3 = p0.rad3;
     c.sh.row_iters = row_iters_for(ctx, p0);
     c.sh.any_nonsquare = 0;
     c.sh.max_nblk = 0;
-    for (uint32_t i : kv.second) {
+    for (uint32_t i : *c.idx) {
       ProdDesc& d = h_desc_[di++];
       d.pl = plans[i];
       d.a = a[i];
@@ -220,18 +239,15 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       d.square = (si || ti) ? (si == ti ? 1 : 0) : ((a[i] == b[i] && na[i] == nb[i]) ? 1 : 0);
       d.xs = si ? si->dev : nullptr;
       d.ys = ti ? ti->dev : nullptr;
+      d.scale[0] = ctw.scale[0];
+      d.scale[1] = ctw.scale[1];
       if (!d.square) c.sh.any_nonsquare = 1;
       c.sh.max_nblk = std::max(c.sh.max_nblk, d.nblk);
       wofs += workspace_words(plans[i]);
       sofs += d.nblk + 1;
     }
-    cls.push_back(c);
   }
-  for (const Cls& c : cls) {                 // tables exist before any capture
-    TwiddleSet tw;
-    rc = get_twiddles(ctx, c.p0, &tw);
-    if (rc) return rc;
-  }
+  uint32_t* heads = sync_ + sofs;     // one queue head per tier
   ProdDesc* descs = d_desc_;
   if (graph) {
     if (graphs_.size() >= 8) {
@@ -267,6 +283,20 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       return from_hip(e);
     }
   }
+  // the queue heads start at zero for every launch (a fill kernel, so that
+  // a captured batch resets them on each replay)
+  if (cls.front().tier >= 0) {
+    e = launch_fill32(heads, kQueueTiers, 0, ctx->stream);
+    if (e != hipSuccess) {
+      if (graph) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(ctx->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipFree(descs);
+      }
+      return from_hip(e);
+    }
+  }
   Marks* marks = ctx->prof;
   if (ctx->prof) ctx->prof->begin(ctx->stream);
   // classes run concurrently on the side streams (not when profiling, whose
@@ -279,7 +309,33 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
     if (e != hipSuccess) nside = 0;
   }
   size_t ci = 0;
-  for (const Cls& c : cls) {
+  // the persistent whole-product launches: one per tier over its classes'
+  // products (contiguous descriptors, longest first)
+  size_t k = 0;
+  while (k < cls.size() && cls[k].tier >= 0 && e == hipSuccess) {
+    const int tier = cls[k].tier;
+    size_t end = k, count = 0, lds = 0;
+    for (; end < cls.size() && cls[end].tier == tier; ++end) {
+      count += cls[end].n;
+      lds = std::max(lds, small_lds_bytes(cls[end].p0));
+    }
+    const hipStream_t st = nside ? side_[ci++ % nside] : ctx->stream;
+    TwiddleSet tw;                    // its root tables serve every length; the scale is per product
+    rc = get_twiddles(ctx, cls[k].p0, &tw);
+    if (rc) break;
+    Work w{};
+    w.many = descs + cls[k].first;
+    w.count = (uint32_t)count;
+    e = launch_small_queue(w, tier, lds, heads + tier, ctx->cs, tw, ctx->d_div, &ctx->h_div, st, marks);
+    if (e == hipSuccess && ctx->timing) {
+      const size_t ev = ctx->timing->record(st);
+      for (size_t j = k; j < end; ++j)
+        for (uint32_t i : *cls[j].idx) ctx->timing->done[tbase + i] = ev;
+    }
+    k = end;
+  }
+  for (; k < cls.size() && !rc && e == hipSuccess; ++k) {
+    const Cls& c = cls[k];
     const hipStream_t st = nside ? side_[ci++ % nside] : ctx->stream;
     TwiddleSet tw;
     rc = get_twiddles(ctx, c.p0, &tw);

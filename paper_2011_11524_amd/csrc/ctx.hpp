@@ -17,6 +17,7 @@ struct TuneTable {
   int row_iters[2][kMaxLogN + 1] = {};
   int path[2][kMaxLogN + 1] = {};   // 0 the default rule, 1 whole-product kernel, 2 pass kernels
   int streams = 0;                  // side streams of a batch's classes (0: kDefaultSideStreams)
+  int queue = 0;                    // 1: whole-product classes of a batch share persistent launches
 };
 constexpr int kMaxSideStreams = 16;
 constexpr int kDefaultSideStreams = 8;

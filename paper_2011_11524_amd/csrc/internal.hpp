@@ -113,6 +113,7 @@ struct ProdDesc {
   int square;               // a == b: one operand transformed
   const uint64_t* xs;       // cached forward transforms of a (2N words: mod p1, mod p2), or null
   const uint64_t* ys;       // the same for b, or null
+  uint64_t scale[2];        // R^2 N^-1 per prime (Montgomery form): read by the queued whole-product kernel
 };
 
 // Whether the forward passes transform operand op (0 = a, 1 = b) of d:
@@ -158,6 +159,16 @@ hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, cons
 bool small_fits(const PlanDev& pl, size_t count);
 hipError_t launch_small(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                         const DivTable* dt, const DivTable* dt_host, hipStream_t stream, Marks* marks);
+// The persistent whole-product kernel over w.many[0 .. count) of mixed
+// lengths of one tier (small_tier), each descriptor with its scale: a grid
+// of what the device holds at once, each workgroup taking products from the
+// queue *head (zero at launch).  lds: the largest small_lds_bytes of them.
+constexpr int kQueueTiers = 3;
+int small_tier(const PlanDev& pl);
+size_t small_lds_bytes(const PlanDev& pl);
+hipError_t launch_small_queue(const Work& w, int tier, size_t lds, uint32_t* head, const Consts& cs,
+                              const TwiddleSet& tw, const DivTable* dt, const DivTable* dt_host,
+                              hipStream_t stream, Marks* marks);
 // Raises a kernel's dynamic-LDS limit to lds_bytes when above the default
 // 64 KB (once per kernel and size: the attribute call is host work).
 hipError_t allow_lds(const void* kernel, size_t lds_bytes);

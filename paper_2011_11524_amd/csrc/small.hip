@@ -12,6 +12,8 @@
 // come first (forward) or last (inverse), around three M-point transforms
 // (Section 7.8).  A batch launches one workgroup per product of the class:
 // the many short products of a batch cost one launch instead of seven.
+#include <algorithm>
+
 #include "rec_dev.hpp"
 
 namespace dmi {
@@ -31,9 +33,14 @@ constexpr size_t small_lds_words(int logm, int f) {
          ((size_t)f << logm) + 2;
 }
 
+// One whole product by the workgroup, in `lds` (small_lds_words(LOGM, F)
+// words); scale[] is R^2 N^-1 in Montgomery form per prime, dt the
+// power-of-ten table in LDS.  Leaves the product in d.out; the caller
+// synchronises the workgroup before `lds` is reused.
 template <int LOGM, bool R3>
-__global__ void __launch_bounds__(kSmallThreads)
-k_small(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g, RecTable rt) {
+__device__ __forceinline__ void small_product(const ProdDesc& d, const Consts& cs, const TwiddleSet& tw,
+                                              const uint64_t (&scale)[2], const DivTable* dt,
+                                              const RecTable& rt, uint64_t* lds) {
   constexpr int LOGE = SmallGeom<LOGM>::LOGE;
   using G = typename SmallGeom<LOGM>::G;
   constexpr int M = G::L, NT = G::NT, S = G::STRIDE;
@@ -42,16 +49,9 @@ k_small(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g, Rec
   constexpr bool kWave = NT <= 64;
   static_assert(NT <= kSmallThreads, "one transform per workgroup at most");
   constexpr int PER_PASS = kSmallThreads / NT;       // sub-transforms run side by side
-  extern __shared__ uint64_t lds[];
   uint64_t* X = lds;                 // operand a, then the product, then q1
   uint64_t* Y = lds + F * S;         // operand b, then q2
   uint64_t* Q = lds + 2 * F * S;     // residues mod p1, then q0, then the digits z
-  __shared__ DivTable sdt;
-  for (unsigned i = threadIdx.x; i < sizeof(DivTable) / 4; i += blockDim.x)
-    reinterpret_cast<uint32_t*>(&sdt)[i] = reinterpret_cast<const uint32_t*>(dt_g)[i];
-  __syncthreads();   // the table is written by some threads and read by all
-  const DivTable* dt = &sdt;
-  const ProdDesc d = load_desc(w);
   const RecConsts rc = rec_consts(rt, d);
   const bool square = d.square != 0;
   const int nsub = square ? F : 2 * F;
@@ -100,7 +100,7 @@ k_small(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g, Rec
     }
     __syncthreads();
     // (inverse length-3 step), the scale R^2 N^-1; residues of p1 go to Q
-    const uint64_t scale = tw.scale[pi];
+    const uint64_t sc = scale[pi];
     for (int q = threadIdx.x; q < M; q += kSmallThreads) {
       const int o = lds_pos<LOGE>(q);
       uint64_t x[F];
@@ -114,7 +114,7 @@ k_small(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g, Rec
       }
 #pragma unroll
       for (int s = 0; s < F; ++s) {
-        const uint64_t v = mont_mul(x[s], scale, P);
+        const uint64_t v = mont_mul(x[s], sc, P);
         if (pi == 0) Q[s * M + q] = v;
         else X[s * S + o] = v;
       }
@@ -177,6 +177,79 @@ k_small(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g, Rec
   }
 }
 
+// The power-of-ten table, copied into the workgroup's LDS.
+__device__ __forceinline__ void load_div_table(DivTable& sdt, const DivTable* __restrict__ dt_g) {
+  for (unsigned i = threadIdx.x; i < sizeof(DivTable) / 4; i += blockDim.x)
+    reinterpret_cast<uint32_t*>(&sdt)[i] = reinterpret_cast<const uint32_t*>(dt_g)[i];
+  __syncthreads();   // the table is written by some threads and read by all
+}
+
+// One workgroup per product of one length (grid.z = product).
+template <int LOGM, bool R3>
+__global__ void __launch_bounds__(kSmallThreads)
+k_small(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g, RecTable rt) {
+  extern __shared__ uint64_t lds[];
+  __shared__ DivTable sdt;
+  load_div_table(sdt, dt_g);
+  small_product<LOGM, R3>(load_desc(w), cs, tw, tw.scale, &sdt, rt, lds);
+}
+
+// Persistent form: a grid sized to what the device holds at once takes the
+// products of w.many[0 .. count), of mixed lengths within one tier (lengths
+// with alike LDS needs), from a queue: each workgroup claims the next
+// product with one atomic increment of *head (zero at launch) and returns
+// once the queue is empty, so every workgroup exits.  Each product carries
+// its own scale.  The host orders the queue longest first.
+// One product of the queue, as a call of its own: each length's body gets
+// its own register allocation instead of the union of every length's.
+template <int LOGM, bool R3>
+__device__ __attribute__((noinline)) void queued_product(const ProdDesc* dp, const Consts* cs,
+                                                         const TwiddleSet* tw, const DivTable* dt,
+                                                         const RecTable* rt, uint64_t* lds) {
+  const ProdDesc d = *dp;
+  small_product<LOGM, R3>(d, *cs, *tw, d.scale, dt, *rt, lds);
+}
+
+// Waves per SIMD the queued kernel of a tier is held to: the occupancy
+// of the per-length kernels of its lengths (their registers decide it).
+constexpr int queue_waves(int tier) { return tier == 0 ? 3 : (tier == 1 ? 2 : 1); }
+
+template <int TIER>
+__global__ void __launch_bounds__(kSmallThreads) __attribute__((amdgpu_waves_per_eu(queue_waves(TIER))))
+k_small_queue(Work w, uint32_t* head, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g,
+              RecTable rt) {
+  extern __shared__ uint64_t lds[];
+  __shared__ DivTable sdt;
+  __shared__ uint32_t slot;
+  load_div_table(sdt, dt_g);
+  for (;;) {
+    __syncthreads();               // the last product's LDS reads, and every read of slot, are done
+    if (threadIdx.x == 0) slot = atomicAdd(head, 1u);
+    __syncthreads();
+    // the same for the whole workgroup: read as a scalar, so the descriptor
+    // below is loaded into scalar registers as with one product per workgroup
+    const uint32_t i = __builtin_amdgcn_readfirstlane(slot);
+    if (i >= w.count) return;
+    const ProdDesc* dp = w.many + i;
+    const int logm = dp->pl.logN;    // sub-transforms of 2^logN points (N = 2^logN or 3 * 2^logN)
+    // only this tier's lengths are compiled in (registers follow the largest)
+#define P2(l) case l: queued_product<l, false>(dp, &cs, &tw, &sdt, &rt, lds); break;
+#define P3(l) case l: queued_product<l, true>(dp, &cs, &tw, &sdt, &rt, lds); break;
+    if constexpr (TIER == 0) {
+      if (dp->pl.rad3) { switch (logm) { P3(4) P3(5) P3(6) P3(7) P3(8) default: break; } }
+      else { switch (logm) { P2(2) P2(3) P2(4) P2(5) P2(6) P2(7) P2(8) default: break; } }
+    } else if constexpr (TIER == 1) {
+      if (dp->pl.rad3) { switch (logm) { P3(9) default: break; } }
+      else { switch (logm) { P2(9) P2(10) default: break; } }
+    } else {
+      if (dp->pl.rad3) { switch (logm) { P3(10) default: break; } }
+      else { switch (logm) { P2(11) P2(12) default: break; } }
+    }
+#undef P2
+#undef P3
+  }
+}
+
 template <int LOGM, bool R3>
 static hipError_t small_launch(const Work& w, const Consts& cs, const TwiddleSet& tw, const DivTable* dt,
                                const RecTable& rt, hipStream_t st) {
@@ -186,6 +259,54 @@ static hipError_t small_launch(const Work& w, const Consts& cs, const TwiddleSet
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(1, 1, w.count), dim3(kSmallThreads), lds, st, w, cs, tw, dt, rt);
   return hipGetLastError();
+}
+
+int small_tier(const PlanDev& pl) {
+  // by the kernels' registers and LDS: tier 0 sub-transforms of up to 2^8
+  // points (N <= 256, or 768 with the factor 3; up to ~133 VGPRs, 19 KB),
+  // tier 1 of 2^9..2^10 (N <= 1024, or 1536; ~214 VGPRs, 38 KB), tier 2
+  // the rest (N <= 4096, or 3072; ~266 VGPRs, 100 KB)
+  return pl.logN <= 8 ? 0 : ((pl.logN <= 10 && !(pl.rad3 && pl.logN == 10)) ? 1 : 2);
+}
+
+size_t small_lds_bytes(const PlanDev& pl) {
+  return small_lds_words((int)pl.logN, pl.rad3 ? 3 : 1) * sizeof(uint64_t);
+}
+
+template <int TIER>
+static hipError_t small_queue_launch(const Work& w, uint32_t* head, size_t lds, const Consts& cs,
+                                     const TwiddleSet& tw, const DivTable* dt, const RecTable& rt,
+                                     hipStream_t st) {
+  auto kern = k_small_queue<TIER>;
+  hipError_t e = allow_lds((const void*)kern, lds);
+  if (e != hipSuccess) return e;
+  // as many workgroups as the device holds at once (the queue balances
+  // the products' uneven work), never more than there are products
+  int per_cu = 0, dev = 0, cus = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, kSmallThreads, lds);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const size_t cap = (size_t)(per_cu > 0 ? per_cu : 1) * (size_t)(cus > 0 ? cus : 1);
+  const unsigned grid = (unsigned)std::min<size_t>(cap, w.count);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kSmallThreads), lds, st, w, head, cs, tw, dt, rt);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_queue(const Work& w, int tier, size_t lds, uint32_t* head, const Consts& cs,
+                              const TwiddleSet& tw, const DivTable* dt, const DivTable* dt_host,
+                              hipStream_t st, Marks* marks) {
+  if (w.count == 0) return hipSuccess;
+  const RecTable rt = make_rec_table(cs, dt_host);
+  hipError_t e = hipErrorInvalidValue;
+  switch (tier) {
+    case 0: e = small_queue_launch<0>(w, head, lds, cs, tw, dt, rt, st); break;
+    case 1: e = small_queue_launch<1>(w, head, lds, cs, tw, dt, rt, st); break;
+    case 2: e = small_queue_launch<2>(w, head, lds, cs, tw, dt, rt, st); break;
+    default: break;
+  }
+  if (e == hipSuccess && marks) marks->mark(kWhole, st);
+  return e;
 }
 
 bool small_fits(const PlanDev& pl, size_t count) {

@@ -12,8 +12,11 @@ candidate launch configuration, and keep the fastest:
     longer-lived workgroups).
 Then the number of side streams over which a batch's classes run
 concurrently is timed on the batched workload (4096 products, operands of
-10^3..10^6 digits).  The table goes to dmul_tune.txt beside the library
-(read by every new context): lines "N row_iters path" and "streams S".
+10^3..10^6 digits), and the persistent whole-product launches (one queue per
+tier of lengths) against one launch per length, on that workload plus a
+batch of 4096 short products (1..1200 limbs).  The table goes to
+dmul_tune.txt beside the library (read by every new context): lines
+"N row_iters path", "streams S" and "queue Q".
 
     python -m paper_2011_11524_amd.tune [--min 7] [--max 21] [--out PATH]
 """
@@ -83,6 +86,7 @@ def main(argv=None) -> int:
     rng = np.random.default_rng(6006)
     os.environ["DMUL_TUNE_TABLE"] = ""        # the tuner's context starts from the defaults
     ctx = dm.Context(0)
+    ctx.tune_queue(False)             # one launch per length while the classes are tuned
     rows = []
     for N in size_classes(args.min, args.max):
         nl = limbs_for_class(N)
@@ -124,6 +128,7 @@ def main(argv=None) -> int:
         a, b = pool.take(int(x)), pool.take(int(y))
         pairs.append((dm.to_device(a), dm.to_device(b)))
         outs.append(torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda"))
+    ctx.tune_queue(False)
     stimes = {}
     for sn in STREAMS:
         ctx.tune_streams(sn)
@@ -131,13 +136,28 @@ def main(argv=None) -> int:
     streams = min(stimes, key=stimes.get)
     print("streams: " + " ".join(f"{k}={v * 1e3:.3f}ms" for k, v in stimes.items()) + f" -> {streams}",
           flush=True)
+    ctx.tune_streams(streams)
+    rng = np.random.default_rng(4007)
+    spairs, souts = [], []
+    for _ in range(4096):
+        a, b = pool.take(int(rng.integers(1, 1200))), pool.take(int(rng.integers(1, 1200)))
+        spairs.append((dm.to_device(a), dm.to_device(b)))
+        souts.append(torch.empty(len(a) + len(b), dtype=torch.uint64, device="cuda"))
+    qtimes = {}
+    for q in (0, 1):
+        ctx.tune_queue(bool(q))
+        qtimes[q] = (time_batch(ctx, pairs, outs, args.reps), time_batch(ctx, spairs, souts, args.reps))
+    queue = min(qtimes, key=lambda q: sum(qtimes[q]))
+    print("queue: " + " ".join(f"{k}={v[0] * 1e3:.3f}+{v[1] * 1e3:.3f}ms" for k, v in qtimes.items()) +
+          f" -> {queue}", flush=True)
     ctx.close()
     with open(args.out, "w") as f:
         f.write("# size-class table written by paper_2011_11524_amd/tune.py: "
-                "N row_iters path (1 whole-product kernel, 2 pass kernels); streams S\n")
+                "N row_iters path (1 whole-product kernel, 2 pass kernels); streams S; queue Q\n")
         for N, best, times in rows:
             f.write(f"{N} {max(1, best[1])} {1 if best[0] == 'whole' else 2}\n")
         f.write(f"streams {streams}\n")
+        f.write(f"queue {queue}\n")
     print(f"wrote {args.out}")
     return 0
 
