@@ -62,8 +62,9 @@ extern "C" {
 #define DMUL_OK 0
 #define DMUL_EINVAL (-1)   /* NULL pointer with nonzero length, overlap, bad flags */
 #define DMUL_EDIGIT (-2)   /* some limb >= 10^19 (found on the device; out unspecified) */
-#define DMUL_ERANGE (-3)   /* transform longer than the device path supports, or a forced k
-                              that breaks the convolution bound */
+#define DMUL_ERANGE (-3)   /* transform longer than the device path supports (N > 2^28:
+                              two passes of at most 2^14 points), or a forced k that breaks
+                              the convolution bound */
 #define DMUL_ENOMEM (-4)   /* workspace above the context budget, or allocation failed */
 #define DMUL_EDEVICE (-5)  /* a HIP runtime error */
 

@@ -16,8 +16,12 @@
 namespace dmi {
 
 constexpr bool kLazy = DMUL_LAZY_FIELD != 0;
-constexpr int kMaxLogN = 26;       // two LDS passes of at most 2^13 points each
-constexpr int kMaxLogLen = 13;     // longest sub-transform held in one workgroup's LDS
+constexpr int kMaxLogN = 28;       // two LDS passes of at most 2^14 points each
+constexpr int kMaxLogLen = 14;     // longest sub-transform held in one workgroup's LDS
+// Up to 2^13 points a pass stages its root tables in LDS next to the data;
+// a 2^14-point row or column (136 KB with padding) leaves no room for them,
+// and its passes read the tables from global memory (L2-resident).
+constexpr int kMaxLogLdsTables = 13;
 constexpr int kMaxLogC3 = 11;      // rows of 3 * 2^logC points: logC <= 11
 constexpr int kMaxLogR3 = 12;      // with C = 3M a column tile holds three columns of 2^logR points
 constexpr int kMinLogN3 = 4;       // lengths 3 * 2^e are used for e >= 4

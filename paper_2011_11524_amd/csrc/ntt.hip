@@ -80,7 +80,8 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
   constexpr bool kTop = LOGR % LOGE == 1 && LOGR > 1;
   static_assert(PER * NTH == R * T, "a tile is whole rows of whole columns");
   extern __shared__ uint64_t lds[];
-  uint64_t* troots = lds + T * G::STRIDE;        // [prime][R/2]
+  constexpr bool kLdsTables = LOGR <= kMaxLogLdsTables;
+  uint64_t* troots = lds + T * G::STRIDE;        // [prime][R/2] when kLdsTables
   const ProdDesc d = load_desc(w);
   const int op = blockIdx.y;
   if (!transforms_operand(d, op)) return;         // squared product, or a cached spectrum
@@ -96,9 +97,11 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
     reinterpret_cast<uint32_t*>(&sdt)[i] = reinterpret_cast<const uint32_t*>(dt_g)[i];
   const DivTable* dt = &sdt;
 
-  for (int i = threadIdx.x; i < R; i += NTH) {
-    const int p = i / (R / 2) , e = i % (R / 2);
-    troots[i] = tw.len_fwd[p][root_table_offset(LOGR) + e];
+  if constexpr (kLdsTables) {
+    for (int i = threadIdx.x; i < R; i += NTH) {
+      const int p = i / (R / 2) , e = i % (R / 2);
+      troots[i] = tw.len_fwd[p][root_table_offset(LOGR) + e];
+    }
   }
   __syncthreads();
   // the split tile, in registers for both primes: point s of the thread is
@@ -120,7 +123,7 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
 #pragma unroll 1
   for (int pi = 0; pi < 2; ++pi) {
     const Prime P = cs.P[pi];
-    const uint64_t* rts = troots + pi * (R / 2);
+    const uint64_t* rts = kLdsTables ? troots + pi * (R / 2) : tw.len_fwd[pi] + root_table_offset(LOGR);
     uint64_t* dst = d.ws + (size_t)(2 * op + pi) * N;
     // the tile of this prime (the groups are below 10^k < p: the same
     // residues for both primes)
@@ -436,9 +439,11 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   // stored to global memory.
   constexpr bool kTop = LOGR % LOGE == 1 && LOGR > 1;
   extern __shared__ uint64_t lds[];
-  uint64_t* troots = lds + T * G::STRIDE;
+  constexpr bool kLdsTables = LOGR <= kMaxLogLdsTables;
   const ProdDesc d = load_desc(w);
   const int pi = blockIdx.y;
+  uint64_t* const troots_l = lds + T * G::STRIDE;
+  const uint64_t* const troots = kLdsTables ? troots_l : tw.len_inv[pi] + root_table_offset(LOGR);
   const Prime P = cs.P[pi];
   uint64_t* X = d.ws + (size_t)pi * d.pl.N;
   const Tile<T, R3> tile(xcd_tile(blockIdx.x, gridDim.x), d.pl.logC, d.pl.rad3);
@@ -447,8 +452,10 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   const int lb = pass_split_bits(d.pl.logC, d.pl.rad3);
   constexpr int R = G::L;
 
-  for (int i = threadIdx.x; i < R / 2; i += blockDim.x)
-    troots[i] = tw.len_inv[pi][root_table_offset(LOGR) + i];
+  if constexpr (kLdsTables) {
+    for (int i = threadIdx.x; i < R / 2; i += blockDim.x)
+      troots_l[i] = tw.len_inv[pi][root_table_offset(LOGR) + i];
+  }
   // Inter-pass factor with the scale, xi_N^(-rev(row) * j) * R^2 N^-1: per
   // thread one column (slot) and a run of consecutive rv = rev(row), the
   // factors a chain f(rv + 1) = f(rv) * xi^-j (xi^-j = xi^(N - j)).
@@ -603,7 +610,8 @@ static hipError_t fwd_cols_launch(const Work& w, const Shape& sh, const Consts& 
   constexpr int T = R3 ? 3 * fwd_triples_per_tile(LOGR) : fwd_cols_per_tile(LOGR);
   constexpr int TS = R3 ? T / 3 : T;
   using G = Geometry<LOGR, LOGE>;
-  const size_t lds = ((size_t)T * G::STRIDE + (size_t)G::L) * sizeof(uint64_t);
+  const size_t tables = LOGR <= kMaxLogLdsTables ? (size_t)G::L : 0;
+  const size_t lds = ((size_t)T * G::STRIDE + tables) * sizeof(uint64_t);
   auto kern = k_fwd_cols<LOGR, LOGE, T, R3>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
@@ -629,8 +637,9 @@ static hipError_t rows_l(const Work& w, const Shape& sh, const Consts& cs, const
                          hipStream_t st) {
   constexpr int LOGE = row_loge(LOGC), RPW = rows_per_wg(LOGC);
   using G = Geometry<LOGC, LOGE>;
-  const size_t lds = ((size_t)RPW * G::STRIDE + (size_t)G::L / 2) * sizeof(uint64_t);
-  auto kern = k_rows<LOGC, LOGE, RPW, INV, true>;
+  constexpr bool TWL = LOGC <= kMaxLogLdsTables;
+  const size_t lds = ((size_t)RPW * G::STRIDE + (TWL ? (size_t)G::L / 2 : 0)) * sizeof(uint64_t);
+  auto kern = k_rows<LOGC, LOGE, RPW, INV, TWL>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
   const uint64_t R = (uint64_t)(sh.rad3 ? 3 : 1) << sh.logR;    // rows of 2^logC points
@@ -659,21 +668,30 @@ constexpr int fused_rows_per_wg(int logl) {
 template <int LOGC>
 static hipError_t rows_fused_l(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                                hipStream_t st) {
-  constexpr int LOGE = fused_loge(LOGC), RPW = fused_rows_per_wg(LOGC);
-  using G = Geometry<LOGC, LOGE>;
-  const size_t lds = ((size_t)RPW * G::STRIDE + (size_t)G::L) * sizeof(uint64_t);
-  auto kern = k_rows_fused<LOGC, LOGE, RPW>;
-  hipError_t e = prepare(kern, lds);
-  if (e != hipSuccess) return e;
-  const uint64_t R = (uint64_t)(sh.rad3 ? 3 : 1) << sh.logR;    // rows of 2^logC points
-  const uint64_t groups = (R + RPW - 1) / RPW;
-  // the tuned loop count, within the same launch-size cap as the row passes
-  const uint64_t cap = groups * 2 * w.count / kRowMinGroups;
-  int iters = sh.row_iters > 0 ? sh.row_iters : 1;
-  if ((uint64_t)iters > cap) iters = cap > 1 ? (int)cap : 1;
-  const unsigned gx = (unsigned)((groups + iters - 1) / iters);
-  hipLaunchKernelGGL(kern, dim3(gx, 2, w.count), dim3(RPW * G::NT), lds, st, w, cs, tw);
-  return hipGetLastError();
+  if constexpr (LOGC > kMaxLogLdsTables) {
+    // rows of 2^14 points leave no room in LDS for the two spectra's root
+    // tables: the forward rows, then the pointwise product with the inverse
+    // rows, as two row passes (the forward spectra go through HBM)
+    hipError_t e = rows_l<LOGC, false>(w, sh, cs, tw, st);
+    if (e == hipSuccess) e = rows_l<LOGC, true>(w, sh, cs, tw, st);
+    return e;
+  } else {
+    constexpr int LOGE = fused_loge(LOGC), RPW = fused_rows_per_wg(LOGC);
+    using G = Geometry<LOGC, LOGE>;
+    const size_t lds = ((size_t)RPW * G::STRIDE + (size_t)G::L) * sizeof(uint64_t);
+    auto kern = k_rows_fused<LOGC, LOGE, RPW>;
+    hipError_t e = prepare(kern, lds);
+    if (e != hipSuccess) return e;
+    const uint64_t R = (uint64_t)(sh.rad3 ? 3 : 1) << sh.logR;    // rows of 2^logC points
+    const uint64_t groups = (R + RPW - 1) / RPW;
+    // the tuned loop count, within the same launch-size cap as the row passes
+    const uint64_t cap = groups * 2 * w.count / kRowMinGroups;
+    int iters = sh.row_iters > 0 ? sh.row_iters : 1;
+    if ((uint64_t)iters > cap) iters = cap > 1 ? (int)cap : 1;
+    const unsigned gx = (unsigned)((groups + iters - 1) / iters);
+    hipLaunchKernelGGL(kern, dim3(gx, 2, w.count), dim3(RPW * G::NT), lds, st, w, cs, tw);
+    return hipGetLastError();
+  }
 }
 
 template <int LOGR, bool R3>
@@ -683,7 +701,8 @@ static hipError_t inv_cols_launch(const Work& w, const Shape& sh, const Consts& 
   constexpr int T = R3 ? 3 * triples_per_tile(LOGR) : cols_per_tile(LOGR);
   constexpr int TS = R3 ? T / 3 : T;
   using G = Geometry<LOGR, LOGE>;
-  const size_t lds = ((size_t)T * G::STRIDE + (size_t)G::L / 2) * sizeof(uint64_t);
+  const size_t tables = LOGR <= kMaxLogLdsTables ? (size_t)G::L / 2 : 0;
+  const size_t lds = ((size_t)T * G::STRIDE + tables) * sizeof(uint64_t);
   auto kern = k_inv_cols<LOGR, LOGE, T, R3>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
@@ -704,7 +723,7 @@ static hipError_t inv_cols_l(const Work& w, const Shape& sh, const Consts& cs, c
   return inv_cols_launch<LOGR, false>(w, sh, cs, tw, st);
 }
 
-#define DMUL_LEN_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13)
+#define DMUL_LEN_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
 
 hipError_t launch_forward(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                           const DivTable* dt, hipStream_t st, Marks* marks) {

@@ -313,7 +313,7 @@ __device__ __forceinline__ uint32_t bitrev(uint32_t i, int bits) {
 }
 
 // Inter-pass factor xi_N^(+-e) (times the inverse scale), e = e_hi*2^lb + e_lo.
-// Exponents are below N <= 2^26 and fit 32 bits.
+// Exponents are below N <= 2^28 and fit 32 bits.
 __device__ __forceinline__ uint64_t pass_factor(const uint64_t* __restrict__ hi,
                                                 const uint64_t* __restrict__ lo, uint32_t e,
                                                 int lb, const Prime& P) {

@@ -132,7 +132,7 @@ hipError_t launch_squares(uint64_t* data, uint32_t n, uint32_t pitch, uint32_t s
 int transpose_inplace(uint64_t* data, uint64_t rows, uint64_t cols, bool bitrev, hipStream_t st) {
   int lr = 0, lc = 0;
   if (!pow2_at_least(rows, kTile, &lr) || !pow2_at_least(cols, kTile, &lc)) return DMUL_EINVAL;
-  if (lr > kMaxLogLen || lc > kMaxLogLen) return DMUL_EINVAL;
+  if (lr > kMaxLogLdsTables || lc > kMaxLogLdsTables) return DMUL_EINVAL;
   hipError_t e = hipSuccess;
   if (rows == cols) {
     if (bitrev) e = launch_permute_rows(data, (uint32_t)rows, (uint32_t)cols, true, true, 0, st);

@@ -40,10 +40,10 @@ def test_strerror():
 
 def _lengths(need, pow2):
     """Transform lengths the planner may pick for `need` coefficients, in
-    increasing order: 2^e (2 <= e <= 26) and, unless pow2, 3*2^e
+    increasing order: 2^e (2 <= e <= 28) and, unless pow2, 3*2^e
     (4 <= e <= 23), each with its R x C layout (log2 R, log2 C)."""
     out = []
-    for e in range(2, 27):
+    for e in range(2, 29):
         out.append((1 << e, 1, e, e // 2))
     if not pow2:
         for e in range(4, 24):

@@ -597,6 +597,48 @@ def test_largest_power_of_two_length(dm, ctx):
     assert z2 == a2 * b2 % (10 ** 19 + 1)
 
 
+def _all_nines_product(na, nb):
+    """Limbs of (10^(19 na) - 1) * (10^(19 nb) - 1) = 10^(19(na+nb)) -
+    10^(19 na) - 10^(19 nb) + 1 for na <= nb: 1, na - 1 zeros, nb - na limbs
+    10^19 - 1, one limb 10^19 - 2, na - 1 limbs 10^19 - 1."""
+    a, b = min(na, nb), max(na, nb)
+    nine = np.uint64(10 ** 19 - 1)
+    z = np.full(a + b, nine, dtype=np.uint64)
+    z[0] = 1
+    z[1:a] = 0
+    z[b] = np.uint64(10 ** 19 - 2)
+    return z
+
+
+@pytest.mark.parametrize("e,na", [(27, 30_000_000), (28, 55_000_000)])
+def test_longest_two_pass_lengths(dm, ctx, e, na):
+    """N = 2^27 (2^13 rows of 2^14 points) and 2^28 (2^14 x 2^14): the
+    2^14-point passes read their root tables from global memory and the
+    2^14-point rows run unfused.  All-nines operands (the convolution's worst
+    case) limb by limb against their closed form, and random operands by
+    their residues modulo 10^19 - 1 and 10^19 + 1 (the oracle's transforms of
+    2^27 and 2^28 points take minutes per prime on the host)."""
+    import torch
+    pl = dm.plan(na, na)
+    assert (pl.N, pl.factor, pl.log2_rows + pl.log2_cols) == (1 << e, 1, e)
+    assert pl.log2_cols == 14 and pl.log2_rows == e - 14
+    _note(f"N=2^{e} {na}x{na} limbs, k={pl.k}, all nines")
+    nines = torch.full((na,), 10 ** 19 - 1, dtype=torch.uint64, device="cuda")
+    got = dm.to_host(ctx.mul(nines, nines))
+    np.testing.assert_array_equal(got, _all_nines_product(na, na))
+    del nines, got
+    _note(f"N=2^{e} {na}x{na - 1234567} limbs, random")
+    rng = np.random.default_rng(2700 + e)
+    a = rng.integers(0, 10 ** 19, size=na, dtype=np.uint64)
+    b = rng.integers(0, 10 ** 19, size=na - 1234567, dtype=np.uint64)
+    assert dm.plan(len(a), len(b)).N == 1 << e
+    z = _gpu_mul(dm, ctx, a, b)
+    assert int(z.max()) < 10 ** 19
+    (a1, a2), (b1, b2), (z1, z2) = _mod_pm(a), _mod_pm(b), _mod_pm(z)
+    assert z1 == a1 * b1 % (10 ** 19 - 1)
+    assert z2 == a2 * b2 % (10 ** 19 + 1)
+
+
 def test_tuned_paths_and_streams(dm):
     """Every kernel path a size-class table may choose (whole-product kernel
     or passes at N <= 4096, any row-loop count) and side-stream counts from
