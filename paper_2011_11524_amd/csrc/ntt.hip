@@ -156,9 +156,9 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
     // start it, one Montgomery product per row after that.
     if constexpr (!R3) {
       constexpr int U = NTH / T;                 // threads per column
-      constexpr int PP = (R + U - 1) / U;        // rows per thread
+      constexpr int PB = R / U, PX = R % U;      // rows per thread: PB, or PB + 1 for the first PX
       const int c = threadIdx.x % T, u = threadIdx.x / T;
-      const int v0 = u * PP, v1 = v0 + PP < R ? v0 + PP : R;
+      const int v0 = u * PB + (u < PX ? u : PX), v1 = v0 + PB + (u < PX ? 1 : 0);
       if (tile.valid(c) && v0 < v1) {
         const uint32_t j = (uint32_t)tile.column(c);
         const uint64_t step = tw.lo_fwd[pi][j];                       // xi^j, j < C <= 2^lb
@@ -173,9 +173,9 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
       const uint64_t* w3 = tw.r3_fwd[pi] + r3_table_offset(d.pl.logC);
       const uint32_t M = (uint32_t)tile.M;
       constexpr int U = NTH / TS;                // threads per column triple
-      constexpr int PP = (R + U - 1) / U;
+      constexpr int PB = R / U, PX = R % U;      // rows per thread: PB, or PB + 1 for the first PX
       const int c = threadIdx.x % TS, u = threadIdx.x / TS;
-      const int v0 = u * PP, v1 = v0 + PP < R ? v0 + PP : R;
+      const int v0 = u * PB + (u < PX ? u : PX), v1 = v0 + PB + (u < PX ? 1 : 0);
       if (tile.valid(c) && v0 < v1) {
         const uint32_t qc = (uint32_t)tile.first + c;
         const uint64_t w31 = w3[qc], w32 = w3[2 * qc];
@@ -464,9 +464,9 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   };
   if constexpr (!R3) {
     constexpr int U = NTH / T;
-    constexpr int PP = (R + U - 1) / U;
+    constexpr int PB = R / U, PX = R % U;        // rows per thread: PB, or PB + 1 for the first PX
     const int c = threadIdx.x % T, u = threadIdx.x / T;
-    const int v0 = u * PP, v1 = v0 + PP < R ? v0 + PP : R;
+    const int v0 = u * PB + (u < PX ? u : PX), v1 = v0 + PB + (u < PX ? 1 : 0);
     const uint32_t j = (uint32_t)tile.column(c);
     const bool ok = tile.valid(c);
     uint64_t f = 0, st = 0;
@@ -487,9 +487,9 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
     const uint64_t* w3 = tw.r3_inv[pi] + r3_table_offset(d.pl.logC);
     const uint32_t M = (uint32_t)tile.M;
     constexpr int U = NTH / TS;
-    constexpr int PP = (R + U - 1) / U;
+    constexpr int PB = R / U, PX = R % U;        // rows per thread: PB, or PB + 1 for the first PX
     const int c = threadIdx.x % TS, u = threadIdx.x / TS;
-    const int v0 = u * PP, v1 = v0 + PP < R ? v0 + PP : R;
+    const int v0 = u * PB + (u < PX ? u : PX), v1 = v0 + PB + (u < PX ? 1 : 0);
     const bool ok = tile.valid(c);
     const uint32_t qc = (uint32_t)tile.first + c;
     uint64_t w31 = 0, w32 = 0, f[3] = {0, 0, 0}, st[3] = {0, 0, 0};
