@@ -163,10 +163,19 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
         const uint32_t j = (uint32_t)tile.column(c);
         const uint64_t step = tw.lo_fwd[pi][j];                       // xi^j, j < C <= 2^lb
         uint64_t f = pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], (uint32_t)v0 * j, lb, P);   // < N
-        for (int rv = v0; rv < v1; ++rv) {
-          const uint32_t row = bitrev((uint32_t)rv, LOGR);
-          dst[row * (uint32_t)C + j] = mont_mul(lds[c * G::STRIDE + lds_pos<LOGE>(row)], f, P);
+        // each row's LDS read is issued one row ahead of its product (the
+        // split tile held for the second prime leaves no registers for more)
+        auto rd = [&](int i) {
+          return v0 + i < v1 ? lds[c * G::STRIDE + lds_pos<LOGE>((int)bitrev((uint32_t)(v0 + i), LOGR))] : 0;
+        };
+        uint64_t x = rd(0);
+#pragma unroll 1
+        for (int i = 0; v0 + i < v1; ++i) {
+          const uint64_t nx = rd(i + 1);
+          const uint32_t row = bitrev((uint32_t)(v0 + i), LOGR);
+          dst[row * (uint32_t)C + j] = mont_mul(x, f, P);
           f = mont_mul(f, step, P);
+          x = nx;
         }
       }
     } else {
@@ -186,21 +195,36 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
           st[sx] = tw.lo_fwd[pi][j];
           f[sx] = pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], (uint32_t)v0 * j, lb, P);
         }
-        for (int rv = v0; rv < v1; ++rv) {
-          const uint32_t row = bitrev((uint32_t)rv, LOGR);
-          const int o = lds_pos<LOGE>((int)row);
-          uint64_t x0 = mont_mul(lds[c * G::STRIDE + o], f[0], P);
-          uint64_t x1 = mont_mul(lds[(TS + c) * G::STRIDE + o], f[1], P);
-          uint64_t x2 = mont_mul(lds[(2 * TS + c) * G::STRIDE + o], f[2], P);
-          dft3(x0, x1, x2, cs.kappa[pi][0], P);
-          x1 = mont_mul(x1, w31, P);
-          x2 = mont_mul(x2, w32, P);
-          uint64_t* rowp = dst + (row * (uint32_t)C + qc);
-          rowp[0] = x0;
-          rowp[M] = x1;
-          rowp[2 * M] = x2;
+        // each row's LDS reads are issued one row ahead of its products (the
+        // split tile held for the second prime leaves no registers for more)
+        auto rd = [&](int i, uint64_t (&x)[3]) {
+          const int o = lds_pos<LOGE>((int)bitrev((uint32_t)(v0 + i), LOGR));
 #pragma unroll
-          for (int sx = 0; sx < 3; ++sx) f[sx] = mont_mul(f[sx], st[sx], P);
+          for (int sx = 0; sx < 3; ++sx) x[sx] = v0 + i < v1 ? lds[(sx * TS + c) * G::STRIDE + o] : 0;
+        };
+        const uint64_t kappa = cs.kappa[pi][0];
+        uint64_t xc[3], xn[3];
+        rd(0, xc);
+#pragma unroll 1
+        for (int i = 0; v0 + i < v1; ++i) {
+          rd(i + 1, xn);
+          {
+            const uint32_t row = bitrev((uint32_t)(v0 + i), LOGR);
+            uint64_t x0 = mont_mul(xc[0], f[0], P);
+            uint64_t x1 = mont_mul(xc[1], f[1], P);
+            uint64_t x2 = mont_mul(xc[2], f[2], P);
+            dft3(x0, x1, x2, kappa, P);
+            x1 = mont_mul(x1, w31, P);
+            x2 = mont_mul(x2, w32, P);
+            uint64_t* rowp = dst + (row * (uint32_t)C + qc);
+            rowp[0] = x0;
+            rowp[M] = x1;
+            rowp[2 * M] = x2;
+#pragma unroll
+            for (int sx = 0; sx < 3; ++sx) f[sx] = mont_mul(f[sx], st[sx], P);
+          }
+#pragma unroll
+          for (int sx = 0; sx < 3; ++sx) xc[sx] = xn[sx];
         }
       }
     }
@@ -462,9 +486,14 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   auto step_inv = [&](uint32_t j) {
     return j ? pass_factor(tw.hi_fwd[pi], tw.lo_fwd[pi], N - j, lb, P) : tw.lo_fwd[pi][0];
   };
+  // Every global load of the thread (its rows, and the factor tables that
+  // start its chain) is issued before the first product that uses one:
+  // the rows are at most PMAX, so they live in registers, and a thread
+  // waits for HBM once instead of once per row.
   if constexpr (!R3) {
     constexpr int U = NTH / T;
     constexpr int PB = R / U, PX = R % U;        // rows per thread: PB, or PB + 1 for the first PX
+    constexpr int PMAX = PB + (PX ? 1 : 0);
     const int c = threadIdx.x % T, u = threadIdx.x / T;
     const int v0 = u * PB + (u < PX ? u : PX), v1 = v0 + PB + (u < PX ? 1 : 0);
     const uint32_t j = (uint32_t)tile.column(c);
@@ -474,24 +503,36 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
       st = step_inv(j);
       f = pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], (uint32_t)v0 * j, lb, P);
     }
-    for (int rv = v0; rv < v1; ++rv) {
-      const uint32_t row = bitrev((uint32_t)rv, LOGR);
-      uint64_t x = 0;
-      if (ok) {
-        x = mont_mul(X[row * (uint32_t)C + j], f, P);
-        f = mont_mul(f, st, P);
+    uint64_t xr[PMAX];
+#pragma unroll
+    for (int i = 0; i < PMAX; ++i) {
+      const int rv = v0 + i;
+      xr[i] = ok && rv < v1 ? X[bitrev((uint32_t)rv, LOGR) * (uint32_t)C + j] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < PMAX; ++i) {
+      const int rv = v0 + i;
+      if (rv < v1) {
+        const uint32_t row = bitrev((uint32_t)rv, LOGR);
+        uint64_t x = 0;
+        if (ok) {
+          x = mont_mul(xr[i], f, P);
+          f = mont_mul(f, st, P);
+        }
+        lds[c * G::STRIDE + lds_pos<LOGE>((int)row)] = x;
       }
-      lds[c * G::STRIDE + lds_pos<LOGE>((int)row)] = x;
     }
   } else {
     const uint64_t* w3 = tw.r3_inv[pi] + r3_table_offset(d.pl.logC);
     const uint32_t M = (uint32_t)tile.M;
     constexpr int U = NTH / TS;
     constexpr int PB = R / U, PX = R % U;        // rows per thread: PB, or PB + 1 for the first PX
+    constexpr int PMAX = PB + (PX ? 1 : 0);
     const int c = threadIdx.x % TS, u = threadIdx.x / TS;
     const int v0 = u * PB + (u < PX ? u : PX), v1 = v0 + PB + (u < PX ? 1 : 0);
     const bool ok = tile.valid(c);
     const uint32_t qc = (uint32_t)tile.first + c;
+    const uint64_t kappa = cs.kappa[pi][1];
     uint64_t w31 = 0, w32 = 0, f[3] = {0, 0, 0}, st[3] = {0, 0, 0};
     if (ok && v0 < v1) {
       w31 = w3[qc];
@@ -503,25 +544,37 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
         f[sx] = pass_factor(tw.hi_inv[pi], tw.lo_inv[pi], (uint32_t)v0 * j, lb, P);
       }
     }
-    for (int rv = v0; rv < v1; ++rv) {
-      const uint32_t row = bitrev((uint32_t)rv, LOGR);
-      const int o = lds_pos<LOGE>((int)row);
-      uint64_t x0 = 0, x1 = 0, x2 = 0;
-      if (ok) {
-        const uint64_t* rowp = X + (row * (uint32_t)C + qc);
-        x0 = rowp[0];
-        x1 = mont_mul(rowp[M], w31, P);
-        x2 = mont_mul(rowp[2 * M], w32, P);
-        dft3(x0, x1, x2, cs.kappa[pi][1], P);
-        x0 = mont_mul(x0, f[0], P);
-        x1 = mont_mul(x1, f[1], P);
-        x2 = mont_mul(x2, f[2], P);
+    uint64_t xr[PMAX][3];
 #pragma unroll
-        for (int sx = 0; sx < 3; ++sx) f[sx] = mont_mul(f[sx], st[sx], P);
+    for (int i = 0; i < PMAX; ++i) {
+      const int rv = v0 + i;
+      const bool in = ok && rv < v1;
+      const uint64_t* rowp = X + (bitrev((uint32_t)rv, LOGR) * (uint32_t)C + qc);
+#pragma unroll
+      for (int sx = 0; sx < 3; ++sx) xr[i][sx] = in ? rowp[sx * M] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < PMAX; ++i) {
+      const int rv = v0 + i;
+      if (rv < v1) {
+        const uint32_t row = bitrev((uint32_t)rv, LOGR);
+        const int o = lds_pos<LOGE>((int)row);
+        uint64_t x0 = 0, x1 = 0, x2 = 0;
+        if (ok) {
+          x0 = xr[i][0];
+          x1 = mont_mul(xr[i][1], w31, P);
+          x2 = mont_mul(xr[i][2], w32, P);
+          dft3(x0, x1, x2, kappa, P);
+          x0 = mont_mul(x0, f[0], P);
+          x1 = mont_mul(x1, f[1], P);
+          x2 = mont_mul(x2, f[2], P);
+#pragma unroll
+          for (int sx = 0; sx < 3; ++sx) f[sx] = mont_mul(f[sx], st[sx], P);
+        }
+        lds[c * G::STRIDE + o] = x0;
+        lds[(TS + c) * G::STRIDE + o] = x1;
+        lds[(2 * TS + c) * G::STRIDE + o] = x2;
       }
-      lds[c * G::STRIDE + o] = x0;
-      lds[(TS + c) * G::STRIDE + o] = x1;
-      lds[(2 * TS + c) * G::STRIDE + o] = x2;
     }
   }
   __syncthreads();
