@@ -291,10 +291,9 @@ int prebuild_pass_tables(dmul_ctx* ctx) {
 }
 
 static void set_twiddles(const dmul_ctx* ctx, const PlanDev& pl, const PassTables& pt, TwiddleSet* tw) {
-  const size_t L1 = ((size_t)1 << kMaxLogLen) - 1;
   for (int i = 0; i < 2; ++i) {
-    tw->len_fwd[i] = ctx->d_roots + (size_t)(2 * i) * L1;
-    tw->len_inv[i] = ctx->d_roots + (size_t)(2 * i + 1) * L1;
+    tw->len_fwd[i] = ctx->d_roots + (size_t)(2 * i) * kRootWords;
+    tw->len_inv[i] = ctx->d_roots + (size_t)(2 * i + 1) * kRootWords;
     tw->r3_fwd[i] = ctx->d_r3 + (size_t)(2 * i) * kR3TableWords;
     tw->r3_inv[i] = ctx->d_r3 + (size_t)(2 * i + 1) * kR3TableWords;
   }
@@ -713,23 +712,30 @@ int dmul_ctx_create(dmul_ctx** out, int device, size_t budget) {
     c->cs.P[i].p_hi = (uint32_t)(kP[i] >> 32);
   }
   c->cs.r_tilde = to_mont(inv_mod(kP[0] % kP[1], kP[1]), kP[1]);
-  // root tables: for every length 2^l, l = 1..kMaxLogLen, w^i (i < 2^(l-1))
-  const size_t L1 = ((size_t)1 << kMaxLogLen) - 1;
-  std::vector<uint64_t> roots(4 * L1);
+  // root tables: for every length 2^l, l = 1..kMaxLogLen, and every stage b
+  // of its butterflies, w^(i * 2^(l-1-b)) for i < 2^b (Montgomery form)
+  std::vector<uint64_t> roots(4 * kRootWords);
   for (int i = 0; i < 2; ++i) {
     const uint64_t p = kP[i];
     for (int l = 1; l <= kMaxLogLen; ++l) {
       const uint64_t w = powmod(kG[i], (p - 1) >> l, p);
       const uint64_t wi = inv_mod(w, p);
-      uint64_t* f = roots.data() + (size_t)(2 * i) * L1 + root_table_offset(l);
-      uint64_t* g = roots.data() + (size_t)(2 * i + 1) * L1 + root_table_offset(l);
+      const size_t half = (size_t)1 << (l - 1);
+      std::vector<uint64_t> fw(half), iw(half);    // w^e, w^-e for e < 2^(l-1)
       uint64_t x = 1, y = 1;
-      for (size_t j = 0; j < ((size_t)1 << (l - 1)); ++j) {
-        f[j] = to_mont(x, p);
-        g[j] = to_mont(y, p);
+      for (size_t e = 0; e < half; ++e) {
+        fw[e] = to_mont(x, p);
+        iw[e] = to_mont(y, p);
         x = mulmod(x, w, p);
         y = mulmod(y, wi, p);
       }
+      uint64_t* f = roots.data() + (size_t)(2 * i) * kRootWords + root_block_offset(l);
+      uint64_t* g = roots.data() + (size_t)(2 * i + 1) * kRootWords + root_block_offset(l);
+      for (int b = 0; b < l; ++b)
+        for (size_t j = 0; j < ((size_t)1 << b); ++j) {
+          f[root_stage_offset(b) + j] = fw[j << (l - 1 - b)];
+          g[root_stage_offset(b) + j] = iw[j << (l - 1 - b)];
+        }
     }
   }
   // radix-3 row tables: for every row length C = 3 * 2^l, l = 0..kMaxLogC3,

@@ -130,7 +130,7 @@ struct dmul_ctx {
   Consts cs{};
   DivTable* d_div = nullptr;
   DivTable h_div{};                     // host copy of the power-of-ten reciprocals
-  uint64_t* d_roots = nullptr;          // [prime][dir] blocks of 2^kMaxLogLen - 1 words
+  uint64_t* d_roots = nullptr;          // [prime][dir] regions of kRootWords words (per-stage root tables)
   uint64_t* d_r3 = nullptr;             // [prime][dir] blocks of kR3TableWords words
   std::map<uint64_t, dmi::PassTables> pass; // by N
   uint64_t* pass_block = nullptr;       // the tables of every length up to kStaticMaxN, built at creation

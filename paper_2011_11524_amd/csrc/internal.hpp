@@ -18,9 +18,11 @@ namespace dmi {
 constexpr bool kLazy = DMUL_LAZY_FIELD != 0;
 constexpr int kMaxLogN = 28;       // two LDS passes of at most 2^14 points each
 constexpr int kMaxLogLen = 14;     // longest sub-transform held in one workgroup's LDS
-// Up to 2^13 points a pass stages its root tables in LDS next to the data;
-// a 2^14-point row or column (136 KB with padding) leaves no room for them,
-// and its passes read the tables from global memory (L2-resident).
+// Rows of up to 2^13 points take the fused row pass (8 points per thread);
+// a 2^14-point row would need 2048 threads there, so such rows run the
+// forward and inverse row passes separately.  (Root tables are staged in
+// LDS wherever they fit beside a pass's data, and read from global memory,
+// L2-resident, where they do not.)
 constexpr int kMaxLogLdsTables = 13;
 constexpr int kMaxLogC3 = 11;      // rows of 3 * 2^logC points: logC <= 11
 constexpr int kMaxLogR3 = 12;      // with C = 3M a column tile holds three columns of 2^logR points
@@ -88,9 +90,17 @@ struct TwiddleSet {
   const uint64_t* lo_inv[2];
 };
 
-// Offset of the table of w_L^i (i < L/2) for L = 2^l inside a per-prime
-// root-table block: tables for l = 1, 2, ... are stored back to back.
-__host__ __device__ constexpr size_t root_table_offset(int l) { return ((size_t)1 << (l - 1)) - 1; }
+// Root tables of a transform of L = 2^l points, one per butterfly stage:
+// the stage on bit b multiplies by w_L^(i * 2^(l-1-b)), i < 2^b (Sections
+// 5.2, 5.3), and its table holds exactly those factors, indexed by i, at
+// offset 2^b - 1 of the length's block (2^l - 1 words).  A stage's factor
+// reads are then contiguous in i, which keeps the lanes of a wavefront on
+// distinct LDS banks (a single table of w^e read at e = i * 2^(l-1-b)
+// would be a strided read).  Blocks for l = 1, 2, ... are stored back to
+// back in a per-prime, per-direction region of kRootWords words.
+__host__ __device__ constexpr size_t root_block_offset(int l) { return ((size_t)1 << l) - (size_t)l - 1; }
+__host__ __device__ constexpr int root_stage_offset(int b) { return (1 << b) - 1; }
+constexpr size_t kRootWords = root_block_offset(kMaxLogLen + 1);
 // Offset of the table of w_C^i (i < 2M) for a row of C = 3M points, M = 2^l,
 // inside a per-prime radix-3 block: tables for l = 0, 1, ... back to back.
 __host__ __device__ constexpr size_t r3_table_offset(int l) { return 2 * (((size_t)1 << l) - 1); }

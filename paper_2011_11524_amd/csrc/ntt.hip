@@ -35,6 +35,18 @@
 
 namespace dmi {
 
+// LDS words a workgroup may use (160 KB per CU, less the static tables).
+constexpr int kLdsWords = (160 * 1024 - 1024) / 8;
+// Whether `lines` transform lines of 2^LOGL points (LDS layout of LOGE) and
+// `tables` per-stage root-table blocks of that length (2^LOGL - 1 words
+// each) fit a workgroup's LDS; where they do not, the kernel reads its
+// root tables from global memory (the same layout, so a stage's reads are
+// contiguous there too).
+template <int LOGL, int LOGE>
+constexpr bool root_tables_fit(int lines, int tables) {
+  return lines * Geometry<LOGL, LOGE>::STRIDE + tables * ((1 << LOGL) - 1) <= kLdsWords;
+}
+
 // ---------------------------------------------------------------------------
 // Pass A tiles.  A tile is T column slots of the R x C matrix.  For C = 2^c
 // they are the T adjacent columns j0 + l.  For C = 3M (R3) they are TS = T/3
@@ -80,8 +92,8 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
   constexpr bool kTop = LOGR % LOGE == 1 && LOGR > 1;
   static_assert(PER * NTH == R * T, "a tile is whole rows of whole columns");
   extern __shared__ uint64_t lds[];
-  constexpr bool kLdsTables = LOGR <= kMaxLogLdsTables;
-  uint64_t* troots = lds + T * G::STRIDE;        // [prime][R/2] when kLdsTables
+  constexpr bool kLdsTables = root_tables_fit<LOGR, LOGE>(T, 2);
+  uint64_t* troots = lds + T * G::STRIDE;        // [prime][R - 1] when kLdsTables
   const ProdDesc d = load_desc(w);
   const int op = blockIdx.y;
   if (!transforms_operand(d, op)) return;         // squared product, or a cached spectrum
@@ -98,9 +110,9 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
   const DivTable* dt = &sdt;
 
   if constexpr (kLdsTables) {
-    for (int i = threadIdx.x; i < R; i += NTH) {
-      const int p = i / (R / 2) , e = i % (R / 2);
-      troots[i] = tw.len_fwd[p][root_table_offset(LOGR) + e];
+    for (int i = threadIdx.x; i < 2 * (R - 1); i += NTH) {
+      const int p = i / (R - 1), e = i % (R - 1);
+      troots[i] = tw.len_fwd[p][root_block_offset(LOGR) + e];
     }
   }
   __syncthreads();
@@ -123,7 +135,7 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
 #pragma unroll 1
   for (int pi = 0; pi < 2; ++pi) {
     const Prime P = cs.P[pi];
-    const uint64_t* rts = kLdsTables ? troots + pi * (R / 2) : tw.len_fwd[pi] + root_table_offset(LOGR);
+    const uint64_t* rts = kLdsTables ? troots + pi * (R - 1) : tw.len_fwd[pi] + root_block_offset(LOGR);
     uint64_t* dst = d.ws + (size_t)(2 * op + pi) * N;
     // the tile of this prime (the groups are below 10^k < p: the same
     // residues for both primes)
@@ -134,7 +146,8 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
         const int row = q / T, sl = q % T;       // row < R/2; v[s + PER/2] is row + R/2
         const uint64_t a = v[s], b = v[s + PER / 2];
         lds[sl * G::STRIDE + lds_pos<LOGE>(row)] = add_mod(a, b, P);
-        lds[sl * G::STRIDE + lds_pos<LOGE>(row + R / 2)] = mont_mul(sub_mod(a, b, P), rts[row], P);
+        lds[sl * G::STRIDE + lds_pos<LOGE>(row + R / 2)] =
+            mont_mul(sub_mod(a, b, P), rts[root_stage_offset(LOGR - 1) + row], P);
       }
     } else {
 #pragma unroll
@@ -269,11 +282,11 @@ k_rows(Work w, Consts cs, TwiddleSet tw) {
   const int r = threadIdx.x / NT, t = threadIdx.x % NT;
   uint64_t* row_lds = lds + r * G::STRIDE;
 
-  const uint64_t* roots_g = (INV ? tw.len_inv[pi] : tw.len_fwd[pi]) + root_table_offset(LOGC);
+  const uint64_t* roots_g = (INV ? tw.len_inv[pi] : tw.len_fwd[pi]) + root_block_offset(LOGC);
   const uint64_t* roots = roots_g;
   if constexpr (TWL) {
     uint64_t* tl = lds + RPW * G::STRIDE;
-    for (int i = threadIdx.x; i < C / 2; i += blockDim.x) tl[i] = roots_g[i];
+    for (int i = threadIdx.x; i < C - 1; i += blockDim.x) tl[i] = roots_g[i];
     roots = tl;
     __syncthreads();
   }
@@ -352,11 +365,19 @@ k_rows_fused(Work w, Consts cs, TwiddleSet tw) {
   const uint32_t groups = (uint32_t)((R + RPW - 1) / RPW);
   const int r = threadIdx.x / NT, t = threadIdx.x % NT;
   uint64_t* row_lds = lds + r * G::STRIDE;
-  uint64_t* rf = lds + RPW * G::STRIDE;          // forward roots of the row length
-  uint64_t* ri = rf + C / 2;                     // inverse roots
-  for (int i = threadIdx.x; i < C / 2; i += blockDim.x) {
-    rf[i] = tw.len_fwd[pi][root_table_offset(LOGC) + i];
-    ri[i] = tw.len_inv[pi][root_table_offset(LOGC) + i];
+  // forward and inverse roots of the row length, staged in LDS where they fit
+  constexpr bool kLdsTables = root_tables_fit<LOGC, LOGE>(RPW, 2);
+  const uint64_t* rf = tw.len_fwd[pi] + root_block_offset(LOGC);
+  const uint64_t* ri = tw.len_inv[pi] + root_block_offset(LOGC);
+  if constexpr (kLdsTables) {
+    uint64_t* lf = lds + RPW * G::STRIDE;
+    uint64_t* li = lf + (C - 1);
+    for (int i = threadIdx.x; i < C - 1; i += blockDim.x) {
+      lf[i] = rf[i];
+      li[i] = ri[i];
+    }
+    rf = lf;
+    ri = li;
   }
   __syncthreads();
 
@@ -463,11 +484,11 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   // stored to global memory.
   constexpr bool kTop = LOGR % LOGE == 1 && LOGR > 1;
   extern __shared__ uint64_t lds[];
-  constexpr bool kLdsTables = LOGR <= kMaxLogLdsTables;
+  constexpr bool kLdsTables = root_tables_fit<LOGR, LOGE>(T, 1);
   const ProdDesc d = load_desc(w);
   const int pi = blockIdx.y;
   uint64_t* const troots_l = lds + T * G::STRIDE;
-  const uint64_t* const troots = kLdsTables ? troots_l : tw.len_inv[pi] + root_table_offset(LOGR);
+  const uint64_t* const troots = kLdsTables ? troots_l : tw.len_inv[pi] + root_block_offset(LOGR);
   const Prime P = cs.P[pi];
   uint64_t* X = d.ws + (size_t)pi * d.pl.N;
   const Tile<T, R3> tile(xcd_tile(blockIdx.x, gridDim.x), d.pl.logC, d.pl.rad3);
@@ -477,8 +498,8 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   constexpr int R = G::L;
 
   if constexpr (kLdsTables) {
-    for (int i = threadIdx.x; i < R / 2; i += blockDim.x)
-      troots_l[i] = tw.len_inv[pi][root_table_offset(LOGR) + i];
+    for (int i = threadIdx.x; i < R - 1; i += blockDim.x)
+      troots_l[i] = tw.len_inv[pi][root_block_offset(LOGR) + i];
   }
   // Inter-pass factor with the scale, xi_N^(-rev(row) * j) * R^2 N^-1: per
   // thread one column (slot) and a run of consecutive rv = rev(row), the
@@ -587,7 +608,7 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
       if (!tile.valid(c)) continue;
       const uint64_t x = canonical<true>(lds[c * G::STRIDE + lds_pos<LOGE>(row)], P);
       const uint64_t y = mont_mul(canonical<true>(lds[c * G::STRIDE + lds_pos<LOGE>(row + R / 2)], P),
-                                  troots[row], P);
+                                  troots[root_stage_offset(LOGR - 1) + row], P);
       const uint32_t j = (uint32_t)tile.column(c);
       X[(uint32_t)row * (uint32_t)C + j] = add_mod(x, y, P);
       X[(uint32_t)(row + R / 2) * (uint32_t)C + j] = sub_mod(x, y, P);
@@ -610,13 +631,14 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
 constexpr int loge_for(int logl) { return logl < 4 ? logl : 4; }
 // Points per thread (log2) in the column passes.
 constexpr int col_loge(int logl) { return loge_for(logl); }
-// LDS words a workgroup may use (160 KB per CU, less the static tables).
-constexpr int kLdsWords = (160 * 1024 - 1024) / 8;
 constexpr int col_stride(int logl) { return (1 << logl) + ((1 << logl) >> col_loge(logl)) + 1; }
 // Column tiles: as many columns as fit a target workgroup size (at most 64)
-// and the LDS next to `extra` words of tables.  Wide tiles matter: every
-// global access of a column pass is a run of T contiguous words of one row,
-// and runs below a 128-byte line waste HBM transactions.
+// and the LDS next to `extra` words (one per point for the forward pass,
+// half a word for the inverse).  Wide tiles matter: every global access of
+// a column pass is a run of T contiguous words of one row, and runs below
+// a 128-byte line waste HBM transactions.  The per-stage root tables take
+// the LDS beside the tile where they fit (root_tables_fit) and are read
+// from global memory otherwise, so they never narrow a tile.
 constexpr int cols_for(int logl, int threads, int extra) {
   int t = 1;
   while (t < 64 && 2 * t * (1 << (logl - col_loge(logl))) <= threads &&
@@ -663,7 +685,7 @@ static hipError_t fwd_cols_launch(const Work& w, const Shape& sh, const Consts& 
   constexpr int T = R3 ? 3 * fwd_triples_per_tile(LOGR) : fwd_cols_per_tile(LOGR);
   constexpr int TS = R3 ? T / 3 : T;
   using G = Geometry<LOGR, LOGE>;
-  const size_t tables = LOGR <= kMaxLogLdsTables ? (size_t)G::L : 0;
+  const size_t tables = root_tables_fit<LOGR, LOGE>(T, 2) ? 2 * ((size_t)G::L - 1) : 0;
   const size_t lds = ((size_t)T * G::STRIDE + tables) * sizeof(uint64_t);
   auto kern = k_fwd_cols<LOGR, LOGE, T, R3>;
   hipError_t e = prepare(kern, lds);
@@ -690,8 +712,8 @@ static hipError_t rows_l(const Work& w, const Shape& sh, const Consts& cs, const
                          hipStream_t st) {
   constexpr int LOGE = row_loge(LOGC), RPW = rows_per_wg(LOGC);
   using G = Geometry<LOGC, LOGE>;
-  constexpr bool TWL = LOGC <= kMaxLogLdsTables;
-  const size_t lds = ((size_t)RPW * G::STRIDE + (TWL ? (size_t)G::L / 2 : 0)) * sizeof(uint64_t);
+  constexpr bool TWL = root_tables_fit<LOGC, LOGE>(RPW, 1);
+  const size_t lds = ((size_t)RPW * G::STRIDE + (TWL ? (size_t)G::L - 1 : 0)) * sizeof(uint64_t);
   auto kern = k_rows<LOGC, LOGE, RPW, INV, TWL>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
@@ -722,16 +744,17 @@ template <int LOGC>
 static hipError_t rows_fused_l(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                                hipStream_t st) {
   if constexpr (LOGC > kMaxLogLdsTables) {
-    // rows of 2^14 points leave no room in LDS for the two spectra's root
-    // tables: the forward rows, then the pointwise product with the inverse
-    // rows, as two row passes (the forward spectra go through HBM)
+    // rows of 2^14 points would need 2048 threads in the fused pass: the
+    // forward rows, then the pointwise product with the inverse rows, as two
+    // row passes (the forward spectra go through HBM)
     hipError_t e = rows_l<LOGC, false>(w, sh, cs, tw, st);
     if (e == hipSuccess) e = rows_l<LOGC, true>(w, sh, cs, tw, st);
     return e;
   } else {
     constexpr int LOGE = fused_loge(LOGC), RPW = fused_rows_per_wg(LOGC);
     using G = Geometry<LOGC, LOGE>;
-    const size_t lds = ((size_t)RPW * G::STRIDE + (size_t)G::L) * sizeof(uint64_t);
+    const size_t tables = root_tables_fit<LOGC, LOGE>(RPW, 2) ? 2 * ((size_t)G::L - 1) : 0;
+    const size_t lds = ((size_t)RPW * G::STRIDE + tables) * sizeof(uint64_t);
     auto kern = k_rows_fused<LOGC, LOGE, RPW>;
     hipError_t e = prepare(kern, lds);
     if (e != hipSuccess) return e;
@@ -754,7 +777,7 @@ static hipError_t inv_cols_launch(const Work& w, const Shape& sh, const Consts& 
   constexpr int T = R3 ? 3 * triples_per_tile(LOGR) : cols_per_tile(LOGR);
   constexpr int TS = R3 ? T / 3 : T;
   using G = Geometry<LOGR, LOGE>;
-  const size_t tables = LOGR <= kMaxLogLdsTables ? (size_t)G::L / 2 : 0;
+  const size_t tables = root_tables_fit<LOGR, LOGE>(T, 1) ? (size_t)G::L - 1 : 0;
   const size_t lds = ((size_t)T * G::STRIDE + tables) * sizeof(uint64_t);
   auto kern = k_inv_cols<LOGR, LOGE, T, R3>;
   hipError_t e = prepare(kern, lds);

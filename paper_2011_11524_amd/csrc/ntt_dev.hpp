@@ -28,7 +28,8 @@ struct Geometry {
 //   F = t + jg*NT,  idx = (F mod 2^lo_b) | (jl << lo_b) | ((F >> lo_b) << (lo_b+nb)).
 // DIF butterflies run from the top bit of the round down, DIT from the
 // bottom up; the factor of the stage on bit b for the pair whose lower
-// point is idx is w^((idx mod 2^b) * 2^(LOGL-1-b)) (Sections 5.2, 5.3, 5.5).
+// point is idx is w^((idx mod 2^b) * 2^(LOGL-1-b)) (Sections 5.2, 5.3, 5.5),
+// entry idx mod 2^b of that stage's root table (tw: the length's block).
 template <int LOGL, int LOGE, bool DIT, int LO_B, int NB>
 struct Round {
   using G = Geometry<LOGL, LOGE>;
@@ -80,8 +81,8 @@ struct Round {
         const int jg = j0 >> NB, jl = j0 & ((1 << NB) - 1);
         const int F = t + jg * G::NT;
         const int lowF = F & ((1 << LO_B) - 1);
-        const int e = (lowF | ((jl & ((1 << lb) - 1)) << LO_B)) << (LOGL - 1 - b);
-        const uint64_t w = tw[e];
+        const int e = lowF | ((jl & ((1 << lb) - 1)) << LO_B);     // idx mod 2^b
+        const uint64_t w = tw[root_stage_offset(b) + e];
         if (DIT) {
           const uint64_t u = mont_mul(y, w, P);
           v[j0] = add_mod(x, u, P);
@@ -120,8 +121,8 @@ struct Round {
         const int jg = j0 >> NB, jl = j0 & ((1 << NB) - 1);
         const int F = t + jg * G::NT;
         const int lowF = F & ((1 << LO_B) - 1);
-        const int e = (lowF | ((jl & ((1 << lb) - 1)) << LO_B)) << (LOGL - 1 - b);
-        const uint64_t w = tw[e];
+        const int e = lowF | ((jl & ((1 << lb) - 1)) << LO_B);     // idx mod 2^b
+        const uint64_t w = tw[root_stage_offset(b) + e];
         if (DIT) {                              // [0, 4p) in and out
           const uint64_t xr = cond_sub(x, p2);  // [0, 2p)
           const uint64_t u = mont_mul_r(y, w, P);   // (0, 2p)

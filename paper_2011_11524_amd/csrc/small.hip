@@ -79,7 +79,7 @@ __device__ __forceinline__ void small_product(const ProdDesc& d, const Consts& c
       }
       __syncthreads();
     }
-    const uint64_t* rf = tw.len_fwd[pi] + root_table_offset(LOGM);
+    const uint64_t* rf = tw.len_fwd[pi] + root_block_offset(LOGM);
     for (int b0 = 0; b0 < nsub; b0 += PER_PASS) {
       const int idx = b0 + (int)threadIdx.x / NT;
       const bool active = (int)threadIdx.x / NT < PER_PASS && idx < nsub;
@@ -92,7 +92,7 @@ __device__ __forceinline__ void small_product(const ProdDesc& d, const Consts& c
       x = mont_mul(x, square ? x : at(Y, n), P);
     }
     __syncthreads();
-    const uint64_t* ri = tw.len_inv[pi] + root_table_offset(LOGM);
+    const uint64_t* ri = tw.len_inv[pi] + root_block_offset(LOGM);
     for (int b0 = 0; b0 < F; b0 += PER_PASS) {
       const int idx = b0 + (int)threadIdx.x / NT;
       const bool active = (int)threadIdx.x / NT < PER_PASS && idx < F;
