@@ -143,6 +143,95 @@ def valu_measured(kernel: str, live_s: float):
             "source": "profiles/c2_10m_counters.json"}
 
 
+# rocprofv3 kernel names of the C2 product's phases (prefix match), and the
+# calibration copy bench.py --copy-probe-mib appends
+PROFILE_KERNELS = {"fwd_cols": "void dmi::k_fwd_cols<", "rows": "void dmi::k_rows_fused<",
+                   "inv_cols": "void dmi::k_inv_cols<", "rec_crt": "void dmi::k_rec_crt<",
+                   "rec_apply": "void dmi::k_rec_apply<", "copy": "__amd_rocclr_copyBuffer"}
+
+
+def _counter_dispatches(path: str) -> dict:
+    """rocprofv3 counter_collection.csv -> {dispatch: {name, ns, counter: value}}."""
+    import csv
+    out = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            e = out.setdefault(int(r["Dispatch_Id"]), {
+                "name": r["Kernel_Name"], "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+            e[r["Counter_Name"]] = float(r["Counter_Value"])
+    return out
+
+
+def _median(xs):
+    xs = sorted(xs)
+    n = len(xs)
+    return xs[n // 2] if n % 2 else 0.5 * (xs[n // 2 - 1] + xs[n // 2])
+
+
+def ingest_profiles(prof_dir: str, copy_mib: int) -> None:
+    """Reads the counter passes of one rocprofv3 session (the subdirectories
+    pmc_valu, pmc_mix, pmc_fetch, pmc_write of prof_dir, each holding
+    c2_counter_collection.csv) and writes profiles/c2_10m_counters.json and
+    profiles/hbm_traffic.json, tagged with the kernel sources' hash: per
+    phase the median of each counter over its dispatches, the duration of
+    the counted dispatches, VALU busy, and HBM bytes (FETCH_SIZE and
+    WRITE_SIZE scaled by what they read for the calibration copy of
+    copy_mib MiB)."""
+    passes = {}
+    for pas in ("valu", "mix", "fetch", "write"):
+        path = os.path.join(prof_dir, "pmc_" + pas, "c2_counter_collection.csv")
+        if os.path.exists(path):
+            passes[pas] = _counter_dispatches(path)
+    kernels, names = {}, {}
+    for phase, prefix in PROFILE_KERNELS.items():
+        ent = {}
+        for pas, disp in passes.items():
+            mine = [e for e in disp.values() if e["name"].startswith(prefix)]
+            if phase == "copy":   # the calibration copy is the largest copy
+                mine = sorted(mine, key=lambda e: e.get("FETCH_SIZE", 0) + e.get("WRITE_SIZE", 0)
+                              + e["ns"])[-1:]
+            if not mine:
+                continue
+            names[phase] = mine[0]["name"]
+            for key in mine[0]:
+                if key not in ("name", "ns"):
+                    ent[key] = _median([e[key] for e in mine])
+            ent["ns_" + pas] = _median([e["ns"] for e in mine])
+            ent["dispatches"] = len(mine)
+        if ent:
+            kernels[phase] = ent
+    copy = kernels.pop("copy", {})
+    copy_kib = copy_mib * 1024.0
+    fetch_scale = copy_kib / copy["FETCH_SIZE"] if copy.get("FETCH_SIZE") else None
+    write_scale = copy_kib / copy["WRITE_SIZE"] if copy.get("WRITE_SIZE") else None
+    for phase, c in kernels.items():
+        if "SQ_ACTIVE_INST_VALU" in c and "ns_valu" in c:
+            c["valu_busy"] = c["SQ_ACTIVE_INST_VALU"] * 4 / (SIMDS * CLOCK_HZ * c["ns_valu"] * 1e-9)
+            c["valu_insts_per_wave"] = c["SQ_INSTS_VALU"] / max(1.0, c.get("SQ_WAVES", 1.0))
+        if "SQ_LDS_BANK_CONFLICT" in c:
+            c["lds_bank_conflict_per_lds_active"] = c["SQ_LDS_BANK_CONFLICT"] / max(1.0, c["SQ_ACTIVE_INST_LDS"])
+        if fetch_scale and write_scale and "FETCH_SIZE" in c and "WRITE_SIZE" in c:
+            c["hbm_bytes"] = 1024.0 * (c["FETCH_SIZE"] * fetch_scale + c["WRITE_SIZE"] * write_scale)
+    src = kernel_source_hash()
+    workload = "10^7 x 10^7 digits, N = 3*2^19"
+    with open(os.path.join(ROOT, "profiles", "c2_10m_counters.json"), "w") as f:
+        json.dump({"source_hash": src, "workload": workload, "kernel_names": names,
+                   "kernels": kernels, "copy": copy, "fetch_scale": fetch_scale,
+                   "write_scale": write_scale}, f, indent=1, sort_keys=True)
+        f.write("\n")
+    if fetch_scale and write_scale:
+        traffic = {k: {"fetch_kib_raw": c["FETCH_SIZE"], "write_kib_raw": c["WRITE_SIZE"],
+                       "bytes_per_launch": c["hbm_bytes"]}
+                   for k, c in kernels.items() if "hbm_bytes" in c}
+        with open(os.path.join(ROOT, "profiles", "hbm_traffic.json"), "w") as f:
+            json.dump({"source_hash": src, "fetch_scale": fetch_scale, "write_scale": write_scale,
+                       "workload": workload, "kernels": traffic,
+                       "summary": "profiles/c2_10m_hbm_counters.md"}, f, indent=1)
+            f.write("\n")
+    for phase, c in kernels.items():
+        print(phase, {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sorted(c.items())})
+
+
 def cpu_baseline(a, b, budget_s: float, max_products: int):
     import oracle
     times = []
@@ -491,6 +580,11 @@ def main() -> int:
                          "without and with the spectrum cache")
     ap.add_argument("--pow2", action="store_true",
                     help="power-of-two transform length even where 3*2^e is shorter")
+    ap.add_argument("--ingest-profiles", default="",
+                    help="write profiles/c2_10m_counters.json and profiles/hbm_traffic.json from the "
+                         "rocprofv3 counter passes under this directory (pmc_valu, pmc_mix, pmc_fetch, "
+                         "pmc_write), taken with --copy-probe-mib (its size is this run's "
+                         "--copy-probe-mib, default 256); no GPU is used")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size (counter calibration)")
     args = ap.parse_args()
@@ -500,6 +594,9 @@ def main() -> int:
               "(independent products shard across GPUs without communication; "
               "see the design notes)", file=sys.stderr)
         return 2
+    if args.ingest_profiles:
+        ingest_profiles(args.ingest_profiles, args.copy_probe_mib or 256)
+        return 0
 
     import numpy as np
     import torch
