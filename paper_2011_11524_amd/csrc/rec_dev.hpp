@@ -139,26 +139,27 @@ __device__ __forceinline__ void crt_digits(uint64_t a1, uint64_t a2, const RecCo
   q2 = rc.Ph * fh + q;
 }
 
-// Carry maps {0,1,2} -> {0,1,2}, two bits per image: bits [2c, 2c+2) = f(c).
-constexpr uint32_t kIdentityMap = 0u | (1u << 2) | (2u << 4);
+// Carry maps {0,1,2} -> {0,1,2}, one byte per argument: byte c holds f(c)
+// for c < 3, and byte 3 holds 3.  Composition is then a byte permute:
+// (later o earlier) has as byte c the byte of `later` that earlier(c)
+// selects, one v_perm_b32 with `earlier` as the selector (byte 3 selects
+// byte 3, which stays 3).
+constexpr uint32_t kIdentityMap = 0x03020100u;
 
 __device__ __forceinline__ uint32_t carry_map(uint64_t s, uint64_t B) {
-  uint32_t m = 0;
+  uint32_t m = 0x03000000u;
 #pragma unroll
   for (uint32_t c = 0; c < 3; ++c) {
     const uint64_t t = s + c;
     const uint32_t o = t >= 2 * B ? 2u : (t >= B ? 1u : 0u);
-    m |= o << (2 * c);
+    m |= o << (8 * c);
   }
   return m;
 }
-__device__ __forceinline__ uint32_t apply_map(uint32_t f, uint32_t c) { return (f >> (2 * c)) & 3u; }
+__device__ __forceinline__ uint32_t apply_map(uint32_t f, uint32_t c) { return (f >> (8 * c)) & 0xffu; }
 // (later o earlier)(c) = later(earlier(c))
 __device__ __forceinline__ uint32_t compose(uint32_t later, uint32_t earlier) {
-  uint32_t m = 0;
-#pragma unroll
-  for (uint32_t c = 0; c < 3; ++c) m |= apply_map(later, apply_map(earlier, c)) << (2 * c);
-  return m;
+  return __builtin_amdgcn_perm(later, later, earlier);
 }
 
 // Exclusive scan of the per-thread maps of one workgroup (thread order =
