@@ -140,8 +140,8 @@ k_rec_apply(Work w, RecTable rt, const DivTable* __restrict__ dt_g) {
   uint64_t* __restrict__ out = d.out;
   __shared__ uint64_t z[BLK + 2];
   __shared__ DivTable sdt;
-  for (unsigned i = threadIdx.x; i < sizeof(DivTable) / 4; i += blockDim.x)
-    reinterpret_cast<uint32_t*>(&sdt)[i] = reinterpret_cast<const uint32_t*>(dt_g)[i];
+  stage_words<kRecThreads, (int)(sizeof(DivTable) / 4)>(reinterpret_cast<uint32_t*>(&sdt),
+                                                        reinterpret_cast<const uint32_t*>(dt_g));
   __syncthreads();   // the table is written by some threads and read by all
   const DivTable* dt = &sdt;
   const uint64_t B = rc.B;
@@ -236,7 +236,7 @@ __global__ void k_fill32(uint32_t* __restrict__ out, size_t n, uint32_t v) {
     out[i] = v;
 }
 
-constexpr int kRecPT = 4;
+constexpr int kRecPT = 5;
 constexpr int kRecBlock = kRecThreads * kRecPT;    // positions per workgroup
 
 size_t recover_blocks(const PlanDev& pl) {

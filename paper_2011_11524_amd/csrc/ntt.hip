@@ -105,15 +105,13 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
   const uint64_t C = tile.C;
   const int lb = pass_split_bits(d.pl.logC, d.pl.rad3);
   __shared__ DivTable sdt;
-  for (unsigned i = threadIdx.x; i < sizeof(DivTable) / 4; i += blockDim.x)
-    reinterpret_cast<uint32_t*>(&sdt)[i] = reinterpret_cast<const uint32_t*>(dt_g)[i];
+  stage_words<NTH, (int)(sizeof(DivTable) / 4)>(reinterpret_cast<uint32_t*>(&sdt),
+                                                 reinterpret_cast<const uint32_t*>(dt_g));
   const DivTable* dt = &sdt;
 
   if constexpr (kLdsTables) {
-    for (int i = threadIdx.x; i < 2 * (R - 1); i += NTH) {
-      const int p = i / (R - 1), e = i % (R - 1);
-      troots[i] = tw.len_fwd[p][root_block_offset(LOGR) + e];
-    }
+    stage_words<NTH, R - 1>(troots, tw.len_fwd[0] + root_block_offset(LOGR));
+    stage_words<NTH, R - 1>(troots + (R - 1), tw.len_fwd[1] + root_block_offset(LOGR));
   }
   __syncthreads();
   // the split tile, in registers for both primes: point s of the thread is
@@ -286,7 +284,7 @@ k_rows(Work w, Consts cs, TwiddleSet tw) {
   const uint64_t* roots = roots_g;
   if constexpr (TWL) {
     uint64_t* tl = lds + RPW * G::STRIDE;
-    for (int i = threadIdx.x; i < C - 1; i += blockDim.x) tl[i] = roots_g[i];
+    stage_words<RPW * NT, C - 1>(tl, roots_g);
     roots = tl;
     __syncthreads();
   }
@@ -372,10 +370,8 @@ k_rows_fused(Work w, Consts cs, TwiddleSet tw) {
   if constexpr (kLdsTables) {
     uint64_t* lf = lds + RPW * G::STRIDE;
     uint64_t* li = lf + (C - 1);
-    for (int i = threadIdx.x; i < C - 1; i += blockDim.x) {
-      lf[i] = rf[i];
-      li[i] = ri[i];
-    }
+    stage_words<RPW * NT, C - 1>(lf, rf);
+    stage_words<RPW * NT, C - 1>(li, ri);
     rf = lf;
     ri = li;
   }
@@ -497,10 +493,7 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   const int lb = pass_split_bits(d.pl.logC, d.pl.rad3);
   constexpr int R = G::L;
 
-  if constexpr (kLdsTables) {
-    for (int i = threadIdx.x; i < R - 1; i += blockDim.x)
-      troots_l[i] = tw.len_inv[pi][root_block_offset(LOGR) + i];
-  }
+  if constexpr (kLdsTables) stage_words<NTH, R - 1>(troots_l, tw.len_inv[pi] + root_block_offset(LOGR));
   // Inter-pass factor with the scale, xi_N^(-rev(row) * j) * R^2 N^-1: per
   // thread one column (slot) and a run of consecutive rv = rev(row), the
   // factors a chain f(rv + 1) = f(rv) * xi^-j (xi^-j = xi^(N - j)).
@@ -603,20 +596,29 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   if constexpr (kTop) {
     DitFrom<LOGR, LOGE, 0, LOGR - 1, kWave>::run(lds + col * G::STRIDE, troots, P, t);
     if constexpr (kWave) __syncthreads();
-    for (int q = threadIdx.x; q < (R / 2) * T; q += blockDim.x) {
+    // a compile-time count of tile positions per thread: the LDS reads of
+    // all of them are issued before the first product
+    static_assert((R / 2) * T % NTH == 0, "whole rows of the tile per thread");
+#pragma unroll
+    for (int s = 0; s < (R / 2) * T / NTH; ++s) {
+      const int q = threadIdx.x + s * NTH;
       const int row = q / T, c = q % T;
-      if (!tile.valid(c)) continue;
-      const uint64_t x = canonical<true>(lds[c * G::STRIDE + lds_pos<LOGE>(row)], P);
-      const uint64_t y = mont_mul(canonical<true>(lds[c * G::STRIDE + lds_pos<LOGE>(row + R / 2)], P),
-                                  troots[root_stage_offset(LOGR - 1) + row], P);
-      const uint32_t j = (uint32_t)tile.column(c);
-      X[(uint32_t)row * (uint32_t)C + j] = add_mod(x, y, P);
-      X[(uint32_t)(row + R / 2) * (uint32_t)C + j] = sub_mod(x, y, P);
+      if (tile.valid(c)) {
+        const uint64_t x = canonical<true>(lds[c * G::STRIDE + lds_pos<LOGE>(row)], P);
+        const uint64_t y = mont_mul(canonical<true>(lds[c * G::STRIDE + lds_pos<LOGE>(row + R / 2)], P),
+                                    troots[root_stage_offset(LOGR - 1) + row], P);
+        const uint32_t j = (uint32_t)tile.column(c);
+        X[(uint32_t)row * (uint32_t)C + j] = add_mod(x, y, P);
+        X[(uint32_t)(row + R / 2) * (uint32_t)C + j] = sub_mod(x, y, P);
+      }
     }
   } else {
     lds_transform<LOGR, LOGE, true, kWave>(lds + col * G::STRIDE, troots, P, t, true);
     if constexpr (kWave) __syncthreads();
-    for (int q = threadIdx.x; q < R * T; q += blockDim.x) {
+    static_assert(R * T % NTH == 0, "whole rows of the tile per thread");
+#pragma unroll
+    for (int s = 0; s < R * T / NTH; ++s) {
+      const int q = threadIdx.x + s * NTH;
       const int row = q / T, c = q % T;
       if (tile.valid(c))
         X[(uint32_t)row * (uint32_t)C + (uint32_t)tile.column(c)] =

@@ -309,6 +309,19 @@ __device__ __forceinline__ uint64_t split_group_nf(const uint64_t* __restrict__ 
   return x;
 }
 
+// dst[i] = src[i] for i < n (global memory to LDS), by the NTH threads of a
+// workgroup with a compile-time stride, so a thread's loads are all issued
+// before its first store (a loop striding by the runtime blockDim.x waits
+// for each load in turn).
+template <int NTH, int n, typename W>
+__device__ __forceinline__ void stage_words(W* __restrict__ dst, const W* __restrict__ src) {
+#pragma unroll
+  for (int s = 0; s < (n + NTH - 1) / NTH; ++s) {
+    const int i = (int)threadIdx.x + s * NTH;
+    if (i < n) dst[i] = src[i];
+  }
+}
+
 __device__ __forceinline__ uint32_t bitrev(uint32_t i, int bits) {
   return bits == 0 ? 0u : (__brev(i) >> (32 - bits));
 }

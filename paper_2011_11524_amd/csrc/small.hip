@@ -179,8 +179,8 @@ __device__ __forceinline__ void small_product(const ProdDesc& d, const Consts& c
 
 // The power-of-ten table, copied into the workgroup's LDS.
 __device__ __forceinline__ void load_div_table(DivTable& sdt, const DivTable* __restrict__ dt_g) {
-  for (unsigned i = threadIdx.x; i < sizeof(DivTable) / 4; i += blockDim.x)
-    reinterpret_cast<uint32_t*>(&sdt)[i] = reinterpret_cast<const uint32_t*>(dt_g)[i];
+  stage_words<kSmallThreads, (int)(sizeof(DivTable) / 4)>(reinterpret_cast<uint32_t*>(&sdt),
+                                                          reinterpret_cast<const uint32_t*>(dt_g));
   __syncthreads();   // the table is written by some threads and read by all
 }
 
