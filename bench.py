@@ -168,11 +168,12 @@ def _median(xs):
     return xs[n // 2] if n % 2 else 0.5 * (xs[n // 2 - 1] + xs[n // 2])
 
 
-def ingest_profiles(prof_dir: str, copy_mib: int) -> None:
+def ingest_profiles(prof_dir: str, copy_mib: int, out_dir: str = "") -> None:
     """Reads the counter passes of one rocprofv3 session (the subdirectories
     pmc_valu, pmc_mix, pmc_fetch, pmc_write of prof_dir, each holding
-    c2_counter_collection.csv) and writes profiles/c2_10m_counters.json and
-    profiles/hbm_traffic.json, tagged with the kernel sources' hash: per
+    c2_counter_collection.csv) and writes c2_10m_counters.json and
+    hbm_traffic.json into out_dir (default profiles/), tagged with the kernel
+    sources' hash: per
     phase the median of each counter over its dispatches, the duration of
     the counted dispatches, VALU busy, and HBM bytes (FETCH_SIZE and
     WRITE_SIZE scaled by what they read for the calibration copy of
@@ -214,7 +215,8 @@ def ingest_profiles(prof_dir: str, copy_mib: int) -> None:
             c["hbm_bytes"] = 1024.0 * (c["FETCH_SIZE"] * fetch_scale + c["WRITE_SIZE"] * write_scale)
     src = kernel_source_hash()
     workload = "10^7 x 10^7 digits, N = 3*2^19"
-    with open(os.path.join(ROOT, "profiles", "c2_10m_counters.json"), "w") as f:
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    with open(os.path.join(out_dir, "c2_10m_counters.json"), "w") as f:
         json.dump({"source_hash": src, "workload": workload, "kernel_names": names,
                    "kernels": kernels, "copy": copy, "fetch_scale": fetch_scale,
                    "write_scale": write_scale}, f, indent=1, sort_keys=True)
@@ -223,7 +225,7 @@ def ingest_profiles(prof_dir: str, copy_mib: int) -> None:
         traffic = {k: {"fetch_kib_raw": c["FETCH_SIZE"], "write_kib_raw": c["WRITE_SIZE"],
                        "bytes_per_launch": c["hbm_bytes"]}
                    for k, c in kernels.items() if "hbm_bytes" in c}
-        with open(os.path.join(ROOT, "profiles", "hbm_traffic.json"), "w") as f:
+        with open(os.path.join(out_dir, "hbm_traffic.json"), "w") as f:
             json.dump({"source_hash": src, "fetch_scale": fetch_scale, "write_scale": write_scale,
                        "workload": workload, "kernels": traffic,
                        "summary": "profiles/c2_10m_hbm_counters.md"}, f, indent=1)
