@@ -47,6 +47,12 @@ constexpr bool root_tables_fit(int lines, int tables) {
   return lines * Geometry<LOGL, LOGE>::STRIDE + tables * ((1 << LOGL) - 1) <= kLdsWords;
 }
 
+// Rows of a column (or column triple) are dealt to its U threads as runs
+// of consecutive rv: PB = R / U each, and one more for PX = R mod U of
+// them.  The PX longer runs are spread evenly over the thread index (thread
+// u has one iff floor((u+1) PX / U) > floor(u PX / U)), so that every
+// wavefront, which a barrier then waits for, gets nearly the same share.
+
 // ---------------------------------------------------------------------------
 // Pass A tiles.  A tile is T column slots of the R x C matrix.  For C = 2^c
 // they are the T adjacent columns j0 + l.  For C = 3M (R3) they are TS = T/3
@@ -167,9 +173,9 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
     // start it, one Montgomery product per row after that.
     if constexpr (!R3) {
       constexpr int U = NTH / T;                 // threads per column
-      constexpr int PB = R / U, PX = R % U;      // rows per thread: PB, or PB + 1 for the first PX
+      constexpr int PB = R / U, PX = R % U;      // rows per thread: PB, or PB + 1 for PX spread ones
       const int c = threadIdx.x % T, u = threadIdx.x / T;
-      const int v0 = u * PB + (u < PX ? u : PX), v1 = v0 + PB + (u < PX ? 1 : 0);
+      const int v0 = u * PB + u * PX / U, v1 = v0 + PB + ((u + 1) * PX / U - u * PX / U);
       if (tile.valid(c) && v0 < v1) {
         const uint32_t j = (uint32_t)tile.column(c);
         const uint64_t step = tw.lo_fwd[pi][j];                       // xi^j, j < C <= 2^lb
@@ -193,9 +199,9 @@ k_fwd_cols(Work w, Consts cs, TwiddleSet tw, const DivTable* __restrict__ dt_g) 
       const uint64_t* w3 = tw.r3_fwd[pi] + r3_table_offset(d.pl.logC);
       const uint32_t M = (uint32_t)tile.M;
       constexpr int U = NTH / TS;                // threads per column triple
-      constexpr int PB = R / U, PX = R % U;      // rows per thread: PB, or PB + 1 for the first PX
+      constexpr int PB = R / U, PX = R % U;      // rows per thread: PB, or PB + 1 for PX spread ones
       const int c = threadIdx.x % TS, u = threadIdx.x / TS;
-      const int v0 = u * PB + (u < PX ? u : PX), v1 = v0 + PB + (u < PX ? 1 : 0);
+      const int v0 = u * PB + u * PX / U, v1 = v0 + PB + ((u + 1) * PX / U - u * PX / U);
       if (tile.valid(c) && v0 < v1) {
         const uint32_t qc = (uint32_t)tile.first + c;
         const uint64_t w31 = w3[qc], w32 = w3[2 * qc];
@@ -506,10 +512,10 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
   // waits for HBM once instead of once per row.
   if constexpr (!R3) {
     constexpr int U = NTH / T;
-    constexpr int PB = R / U, PX = R % U;        // rows per thread: PB, or PB + 1 for the first PX
+    constexpr int PB = R / U, PX = R % U;        // rows per thread: PB, or PB + 1 for PX spread ones
     constexpr int PMAX = PB + (PX ? 1 : 0);
     const int c = threadIdx.x % T, u = threadIdx.x / T;
-    const int v0 = u * PB + (u < PX ? u : PX), v1 = v0 + PB + (u < PX ? 1 : 0);
+    const int v0 = u * PB + u * PX / U, v1 = v0 + PB + ((u + 1) * PX / U - u * PX / U);
     const uint32_t j = (uint32_t)tile.column(c);
     const bool ok = tile.valid(c);
     uint64_t f = 0, st = 0;
@@ -540,10 +546,10 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
     const uint64_t* w3 = tw.r3_inv[pi] + r3_table_offset(d.pl.logC);
     const uint32_t M = (uint32_t)tile.M;
     constexpr int U = NTH / TS;
-    constexpr int PB = R / U, PX = R % U;        // rows per thread: PB, or PB + 1 for the first PX
+    constexpr int PB = R / U, PX = R % U;        // rows per thread: PB, or PB + 1 for PX spread ones
     constexpr int PMAX = PB + (PX ? 1 : 0);
     const int c = threadIdx.x % TS, u = threadIdx.x / TS;
-    const int v0 = u * PB + (u < PX ? u : PX), v1 = v0 + PB + (u < PX ? 1 : 0);
+    const int v0 = u * PB + u * PX / U, v1 = v0 + PB + ((u + 1) * PX / U - u * PX / U);
     const bool ok = tile.valid(c);
     const uint32_t qc = (uint32_t)tile.first + c;
     const uint64_t kappa = cs.kappa[pi][1];
