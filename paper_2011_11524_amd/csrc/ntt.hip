@@ -37,14 +37,21 @@ namespace dmi {
 
 // LDS words a workgroup may use (160 KB per CU, less the static tables).
 constexpr int kLdsWords = (160 * 1024 - 1024) / 8;
-// Whether `lines` transform lines of 2^LOGL points (LDS layout of LOGE) and
-// `tables` per-stage root-table blocks of that length (2^LOGL - 1 words
-// each) fit a workgroup's LDS; where they do not, the kernel reads its
-// root tables from global memory (the same layout, so a stage's reads are
-// contiguous there too).
+// Whether a workgroup holding `lines` transform lines of 2^LOGL points
+// (LDS layout of LOGE) stages its `tables` per-stage root-table blocks of
+// that length (2^LOGL - 1 words each) in LDS: where they fit, and where
+// they would not cost the CU its second workgroup (lines that leave room
+// for two workgroups without the tables, but only one with them).  Else
+// the kernel reads its root tables from global memory (L2-resident, the
+// same layout, so a stage's reads are contiguous there too): measured on
+// the fused row pass, 4096-point rows run 12-14% faster that way (two
+// workgroups per CU instead of one), 2048-point rows 12% slower (four
+// instead of three).
 template <int LOGL, int LOGE>
 constexpr bool root_tables_fit(int lines, int tables) {
-  return lines * Geometry<LOGL, LOGE>::STRIDE + tables * ((1 << LOGL) - 1) <= kLdsWords;
+  const int data = lines * Geometry<LOGL, LOGE>::STRIDE;
+  const int with = data + tables * ((1 << LOGL) - 1);
+  return with <= kLdsWords && !(2 * data <= kLdsWords && 2 * with > kLdsWords);
 }
 
 // Rows of a column (or column triple) are dealt to its U threads as runs
