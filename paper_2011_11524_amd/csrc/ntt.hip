@@ -646,7 +646,17 @@ k_inv_cols(Work w, Consts cs, TwiddleSet tw) {
 constexpr int loge_for(int logl) { return logl < 4 ? logl : 4; }
 // Points per thread (log2) in the column passes.
 constexpr int col_loge(int logl) { return loge_for(logl); }
-constexpr int col_stride(int logl) { return (1 << logl) + ((1 << logl) >> col_loge(logl)) + 1; }
+// Launches too small to give every CU a workgroup (a lone short product)
+// take a lean configuration for transforms of up to 2^kLeanMaxLog points:
+// 4 points per thread, so the same transform runs on four times the
+// threads in a quarter of the per-thread chain, and narrower tiles (more
+// workgroups).  A 10^5-digit product (N = 3*2^12) runs 0.065 -> 0.045 ms
+// that way; in the batched workload, whose launches are large, it costs 2%,
+// so those keep 16 points per thread.
+constexpr int kLeanMaxLog = 7;
+constexpr int lean_loge(int logl) { return logl < 2 ? logl : 2; }
+constexpr int kLeanMinGroups = 256;   // one workgroup per CU
+constexpr int col_stride(int logl, int loge) { return (1 << logl) + ((1 << logl) >> loge) + 1; }
 // Column tiles: as many columns as fit a target workgroup size (at most 64)
 // and the LDS next to `extra` words (one per point for the forward pass,
 // half a word for the inverse).  Wide tiles matter: every global access of
@@ -654,19 +664,18 @@ constexpr int col_stride(int logl) { return (1 << logl) + ((1 << logl) >> col_lo
 // a 128-byte line waste HBM transactions.  The per-stage root tables take
 // the LDS beside the tile where they fit (root_tables_fit) and are read
 // from global memory otherwise, so they never narrow a tile.
-constexpr int cols_for(int logl, int threads, int extra) {
+constexpr int cols_for(int logl, int loge, int threads, int extra) {
   int t = 1;
-  while (t < 64 && 2 * t * (1 << (logl - col_loge(logl))) <= threads &&
-         2 * t * col_stride(logl) + extra <= kLdsWords)
+  while (t < 64 && 2 * t * (1 << (logl - loge)) <= threads && 2 * t * col_stride(logl, loge) + extra <= kLdsWords)
     t *= 2;
   return t;
 }
 // Column triples per tile (C = 3M): the largest power of two, 1..16, within
 // the thread target and the LDS.
-constexpr int triples_for(int logl, int threads, int extra) {
+constexpr int triples_for(int logl, int loge, int threads, int extra) {
   int t = 1;
-  while (t < 16 && 2 * t * 3 * (1 << (logl - col_loge(logl))) <= threads &&
-         2 * t * 3 * col_stride(logl) + extra <= kLdsWords)
+  while (t < 16 && 2 * t * 3 * (1 << (logl - loge)) <= threads &&
+         2 * t * 3 * col_stride(logl, loge) + extra <= kLdsWords)
     t *= 2;
   return t;
 }
@@ -676,10 +685,12 @@ constexpr int triples_for(int logl, int threads, int extra) {
 // 512 threads: there the forward tile takes 1024 threads and 8 columns,
 // whose register cap of 128 costs a small spill but took C3's forward
 // column pass from 198 to 173 us.
-constexpr int fwd_cols_per_tile(int logl) { return cols_for(logl, logl >= 11 ? 1024 : 512, 1 << logl); }
-constexpr int cols_per_tile(int logl) { return cols_for(logl, 1024, (1 << logl) / 2); }
-constexpr int fwd_triples_per_tile(int logl) { return triples_for(logl, 768, 1 << logl); }
-constexpr int triples_per_tile(int logl) { return triples_for(logl, 1024, (1 << logl) / 2); }
+constexpr int fwd_cols_per_tile(int logl, int loge) {
+  return cols_for(logl, loge, logl >= 11 ? 1024 : 512, 1 << logl);
+}
+constexpr int cols_per_tile(int logl, int loge) { return cols_for(logl, loge, 1024, (1 << logl) / 2); }
+constexpr int fwd_triples_per_tile(int logl, int loge) { return triples_for(logl, loge, 768, 1 << logl); }
+constexpr int triples_per_tile(int logl, int loge) { return triples_for(logl, loge, 1024, (1 << logl) / 2); }
 constexpr uint64_t kRowMinGroups = 1024;
 // Points per thread (log2) and rows per workgroup in the row passes.
 constexpr int row_loge(int logl) { return loge_for(logl); }
@@ -693,33 +704,55 @@ static hipError_t prepare(K kernel, size_t lds_bytes) {
   return allow_lds((const void*)kernel, lds_bytes);
 }
 
-template <int LOGR, bool R3>
+// Column tiles (slots per tile) and workgroups of a column-pass launch.
+template <int LOGR, int LOGE, bool R3, bool FWD>
+struct ColLaunch {
+  static constexpr int T = R3 ? 3 * (FWD ? fwd_triples_per_tile(LOGR, LOGE) : triples_per_tile(LOGR, LOGE))
+                              : (FWD ? fwd_cols_per_tile(LOGR, LOGE) : cols_per_tile(LOGR, LOGE));
+  static constexpr int TS = R3 ? T / 3 : T;
+  static uint64_t tiles(const Shape& sh) {
+    const uint64_t span = R3 ? (uint64_t)1 << sh.logC : row_len(sh.logC, 0);   // tiles cover M or C
+    return (span + TS - 1) / TS;
+  }
+};
+
+template <int LOGR, int LOGE, bool R3>
 static hipError_t fwd_cols_launch(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                                   const DivTable* dt, hipStream_t st) {
-  constexpr int LOGE = col_loge(LOGR);
-  constexpr int T = R3 ? 3 * fwd_triples_per_tile(LOGR) : fwd_cols_per_tile(LOGR);
-  constexpr int TS = R3 ? T / 3 : T;
+  constexpr int T = ColLaunch<LOGR, LOGE, R3, true>::T;
   using G = Geometry<LOGR, LOGE>;
   const size_t tables = root_tables_fit<LOGR, LOGE>(T, 2) ? 2 * ((size_t)G::L - 1) : 0;
   const size_t lds = ((size_t)T * G::STRIDE + tables) * sizeof(uint64_t);
   auto kern = k_fwd_cols<LOGR, LOGE, T, R3>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
-  const uint64_t span = R3 ? (uint64_t)1 << sh.logC : row_len(sh.logC, 0);   // tiles cover M or C
-  dim3 grid((unsigned)((span + TS - 1) / TS), sh.any_nonsquare ? 2 : 1, w.count);
+  dim3 grid((unsigned)ColLaunch<LOGR, LOGE, R3, true>::tiles(sh), sh.any_nonsquare ? 2 : 1, w.count);
   hipLaunchKernelGGL(kern, grid, dim3(T * G::NT), lds, st, w, cs, tw, dt);
   return hipGetLastError();
+}
+
+// The default configuration, or the lean one where the default launch
+// would leave CUs without a workgroup.
+template <int LOGR, bool R3>
+static hipError_t fwd_cols_pick(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                                const DivTable* dt, hipStream_t st) {
+  constexpr int LOGE = col_loge(LOGR);
+  if constexpr (LOGR <= kLeanMaxLog && lean_loge(LOGR) != LOGE) {
+    const uint64_t wgs = ColLaunch<LOGR, LOGE, R3, true>::tiles(sh) * (sh.any_nonsquare ? 2 : 1) * w.count;
+    if (wgs < kLeanMinGroups) return fwd_cols_launch<LOGR, lean_loge(LOGR), R3>(w, sh, cs, tw, dt, st);
+  }
+  return fwd_cols_launch<LOGR, LOGE, R3>(w, sh, cs, tw, dt, st);
 }
 
 template <int LOGR>
 static hipError_t fwd_cols_l(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                              const DivTable* dt, hipStream_t st) {
   if constexpr (LOGR <= kMaxLogR3) {
-    if (sh.rad3) return fwd_cols_launch<LOGR, true>(w, sh, cs, tw, dt, st);
+    if (sh.rad3) return fwd_cols_pick<LOGR, true>(w, sh, cs, tw, dt, st);
   } else {
     if (sh.rad3) return hipErrorInvalidValue;
   }
-  return fwd_cols_launch<LOGR, false>(w, sh, cs, tw, dt, st);
+  return fwd_cols_pick<LOGR, false>(w, sh, cs, tw, dt, st);
 }
 
 template <int LOGC, bool INV>
@@ -751,8 +784,34 @@ static hipError_t rows_l(const Work& w, const Shape& sh, const Consts& cs, const
 // the long rows need about 170 registers (two wavefronts per SIMD): the
 // fused pass of C2's 1024-point rows took 60 us that way, 52 us this way.
 constexpr int fused_loge(int logl) { return logl <= 8 ? loge_for(logl) : 3; }
-constexpr int fused_rows_per_wg(int logl) {
-  return (kRowThreads >> (logl - fused_loge(logl))) < 1 ? 1 : (kRowThreads >> (logl - fused_loge(logl)));
+constexpr int fused_rows_per_wg(int logl, int loge) {
+  return (kRowThreads >> (logl - loge)) < 1 ? 1 : (kRowThreads >> (logl - loge));
+}
+
+// Workgroups of a fused row-pass launch: row groups over the tuned loop
+// count, within the same launch-size cap as the row passes.
+static unsigned fused_groups_x(const Shape& sh, uint32_t count, int rpw) {
+  const uint64_t R = (uint64_t)(sh.rad3 ? 3 : 1) << sh.logR;    // rows of 2^logC points
+  const uint64_t groups = (R + rpw - 1) / rpw;
+  const uint64_t cap = groups * 2 * count / kRowMinGroups;
+  int iters = sh.row_iters > 0 ? sh.row_iters : 1;
+  if ((uint64_t)iters > cap) iters = cap > 1 ? (int)cap : 1;
+  return (unsigned)((groups + iters - 1) / iters);
+}
+
+template <int LOGC, int LOGE>
+static hipError_t rows_fused_launch(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                                    hipStream_t st) {
+  constexpr int RPW = fused_rows_per_wg(LOGC, LOGE);
+  using G = Geometry<LOGC, LOGE>;
+  const size_t tables = root_tables_fit<LOGC, LOGE>(RPW, 2) ? 2 * ((size_t)G::L - 1) : 0;
+  const size_t lds = ((size_t)RPW * G::STRIDE + tables) * sizeof(uint64_t);
+  auto kern = k_rows_fused<LOGC, LOGE, RPW>;
+  hipError_t e = prepare(kern, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(fused_groups_x(sh, w.count, RPW), 2, w.count), dim3(RPW * G::NT), lds, st, w,
+                     cs, tw);
+  return hipGetLastError();
 }
 
 template <int LOGC>
@@ -766,52 +825,50 @@ static hipError_t rows_fused_l(const Work& w, const Shape& sh, const Consts& cs,
     if (e == hipSuccess) e = rows_l<LOGC, true>(w, sh, cs, tw, st);
     return e;
   } else {
-    constexpr int LOGE = fused_loge(LOGC), RPW = fused_rows_per_wg(LOGC);
-    using G = Geometry<LOGC, LOGE>;
-    const size_t tables = root_tables_fit<LOGC, LOGE>(RPW, 2) ? 2 * ((size_t)G::L - 1) : 0;
-    const size_t lds = ((size_t)RPW * G::STRIDE + tables) * sizeof(uint64_t);
-    auto kern = k_rows_fused<LOGC, LOGE, RPW>;
-    hipError_t e = prepare(kern, lds);
-    if (e != hipSuccess) return e;
-    const uint64_t R = (uint64_t)(sh.rad3 ? 3 : 1) << sh.logR;    // rows of 2^logC points
-    const uint64_t groups = (R + RPW - 1) / RPW;
-    // the tuned loop count, within the same launch-size cap as the row passes
-    const uint64_t cap = groups * 2 * w.count / kRowMinGroups;
-    int iters = sh.row_iters > 0 ? sh.row_iters : 1;
-    if ((uint64_t)iters > cap) iters = cap > 1 ? (int)cap : 1;
-    const unsigned gx = (unsigned)((groups + iters - 1) / iters);
-    hipLaunchKernelGGL(kern, dim3(gx, 2, w.count), dim3(RPW * G::NT), lds, st, w, cs, tw);
-    return hipGetLastError();
+    constexpr int LOGE = fused_loge(LOGC);
+    if constexpr (LOGC <= kLeanMaxLog && lean_loge(LOGC) != LOGE) {
+      const uint64_t wgs = (uint64_t)fused_groups_x(sh, w.count, fused_rows_per_wg(LOGC, LOGE)) * 2 * w.count;
+      if (wgs < kLeanMinGroups) return rows_fused_launch<LOGC, lean_loge(LOGC)>(w, sh, cs, tw, st);
+    }
+    return rows_fused_launch<LOGC, LOGE>(w, sh, cs, tw, st);
   }
 }
 
-template <int LOGR, bool R3>
+template <int LOGR, int LOGE, bool R3>
 static hipError_t inv_cols_launch(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                                   hipStream_t st) {
-  constexpr int LOGE = col_loge(LOGR);
-  constexpr int T = R3 ? 3 * triples_per_tile(LOGR) : cols_per_tile(LOGR);
-  constexpr int TS = R3 ? T / 3 : T;
+  constexpr int T = ColLaunch<LOGR, LOGE, R3, false>::T;
   using G = Geometry<LOGR, LOGE>;
   const size_t tables = root_tables_fit<LOGR, LOGE>(T, 1) ? (size_t)G::L - 1 : 0;
   const size_t lds = ((size_t)T * G::STRIDE + tables) * sizeof(uint64_t);
   auto kern = k_inv_cols<LOGR, LOGE, T, R3>;
   hipError_t e = prepare(kern, lds);
   if (e != hipSuccess) return e;
-  const uint64_t span = R3 ? (uint64_t)1 << sh.logC : row_len(sh.logC, 0);
-  dim3 grid((unsigned)((span + TS - 1) / TS), 2, w.count);
+  dim3 grid((unsigned)ColLaunch<LOGR, LOGE, R3, false>::tiles(sh), 2, w.count);
   hipLaunchKernelGGL(kern, grid, dim3(T * G::NT), lds, st, w, cs, tw);
   return hipGetLastError();
+}
+
+template <int LOGR, bool R3>
+static hipError_t inv_cols_pick(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
+                                hipStream_t st) {
+  constexpr int LOGE = col_loge(LOGR);
+  if constexpr (LOGR <= kLeanMaxLog && lean_loge(LOGR) != LOGE) {
+    const uint64_t wgs = ColLaunch<LOGR, LOGE, R3, false>::tiles(sh) * 2 * w.count;
+    if (wgs < kLeanMinGroups) return inv_cols_launch<LOGR, lean_loge(LOGR), R3>(w, sh, cs, tw, st);
+  }
+  return inv_cols_launch<LOGR, LOGE, R3>(w, sh, cs, tw, st);
 }
 
 template <int LOGR>
 static hipError_t inv_cols_l(const Work& w, const Shape& sh, const Consts& cs, const TwiddleSet& tw,
                              hipStream_t st) {
   if constexpr (LOGR <= kMaxLogR3) {
-    if (sh.rad3) return inv_cols_launch<LOGR, true>(w, sh, cs, tw, st);
+    if (sh.rad3) return inv_cols_pick<LOGR, true>(w, sh, cs, tw, st);
   } else {
     if (sh.rad3) return hipErrorInvalidValue;
   }
-  return inv_cols_launch<LOGR, false>(w, sh, cs, tw, st);
+  return inv_cols_pick<LOGR, false>(w, sh, cs, tw, st);
 }
 
 #define DMUL_LEN_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
