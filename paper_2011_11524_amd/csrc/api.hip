@@ -488,7 +488,8 @@ static int enqueue_one(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64
   if (rc) return rc;
   rc = ensure_workspace(ctx, workspace_words(pl));
   if (rc) return rc;
-  rc = ensure_rec_sync(ctx, recover_blocks(pl) + 1);
+  const bool rec_lean = recover_lean(pl);
+  rc = ensure_rec_sync(ctx, recover_blocks(pl, rec_lean) + 1);
   if (rc) return rc;
   Work w{};
   ProdDesc& d = w.one;
@@ -499,13 +500,13 @@ static int enqueue_one(dmul_ctx* ctx, const uint64_t* a, size_t na, const uint64
   d.ws = ctx->ws;
   d.status = status;
   d.rec_sync = ctx->rec_sync;
-  d.nblk = (uint32_t)recover_blocks(pl);
+  d.nblk = (uint32_t)recover_blocks(pl, rec_lean);
   d.square = (sa || sb) ? (sa == sb ? 1 : 0) : ((a == b && na == nb) ? 1 : 0);
   d.xs = sa ? sa->dev : nullptr;
   d.ys = sb ? sb->dev : nullptr;
   w.many = nullptr;
   w.count = 1;
-  Shape sh{pl.logR, pl.logC, pl.rad3, d.square ? 0 : 1, row_iters_for(ctx, pl), d.nblk};
+  Shape sh{pl.logR, pl.logC, pl.rad3, d.square ? 0 : 1, row_iters_for(ctx, pl), d.nblk, rec_lean ? 1 : 0};
   if (ctx->poison) {
     hipError_t e = launch_fill32(ctx->ws, 2 * workspace_words(pl), kPoison, ctx->stream);
     if (e == hipSuccess) e = launch_fill32(ctx->rec_sync, d.nblk + 1, kPoison, ctx->stream);
@@ -939,10 +940,11 @@ int dmul_ex_noalloc(dmul_ctx* c, const uint64_t* a, size_t na, const uint64_t* b
   d.ws = c->scratch;
   d.status = c->d_status;
   d.rec_sync = (uint32_t*)(c->scratch + 4 * kStaticMaxN);
-  d.nblk = (uint32_t)recover_blocks(pl);
+  const bool rec_lean = recover_lean(pl);
+  d.nblk = (uint32_t)recover_blocks(pl, rec_lean);
   d.square = (a == b && na == nb) ? 1 : 0;
   w.count = 1;
-  const Shape sh{pl.logR, pl.logC, pl.rad3, d.square ? 0 : 1, row_iters_for(c, pl), d.nblk};
+  const Shape sh{pl.logR, pl.logC, pl.rad3, d.square ? 0 : 1, row_iters_for(c, pl), d.nblk, rec_lean ? 1 : 0};
   hipError_t e = hipSuccess;
   if (c->poison) {
     e = launch_fill32(d.ws, 2 * workspace_words(pl), kPoison, c->stream);
@@ -1159,7 +1161,7 @@ int dmul_spectrum_create(dmul_ctx* c, const uint64_t* a, size_t na, size_t nb, u
   d.status = c->d_status;
   d.square = 1;
   w.count = 1;
-  const Shape sh{pl.logR, pl.logC, pl.rad3, 0, row_iters_for(c, pl), 0};
+  const Shape sh{pl.logR, pl.logC, pl.rad3, 0, row_iters_for(c, pl), 0, 0};
   e = launch_forward(w, sh, c->cs, tw, c->d_div, c->stream, nullptr);
   if (e != hipSuccess) {
     if (s->owned) (void)hipFree(s->dev);

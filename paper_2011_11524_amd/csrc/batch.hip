@@ -181,7 +181,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
     }
     classes[{plans[i].N, (spec_a(i) || spec_b(i)) ? 1 : 0}].push_back((uint32_t)i);
     ws_words += workspace_words(plans[i]);
-    sync_words += recover_blocks(plans[i]) + 1;
+    sync_words += recover_blocks(plans[i], false) + 1;
     ++nvalid;
   }
   if (nvalid == 0) return DMUL_OK;
@@ -224,6 +224,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
     c.sh.row_iters = row_iters_for(ctx, p0);
     c.sh.any_nonsquare = 0;
     c.sh.max_nblk = 0;
+    c.sh.rec_lean = 0;
     for (uint32_t i : *c.idx) {
       ProdDesc& d = h_desc_[di++];
       d.pl = plans[i];
@@ -233,7 +234,7 @@ int BatchEngine::run(dmul_ctx* ctx, size_t count, const uint64_t* const* a, cons
       d.ws = ws_ + wofs;
       d.status = status_dev + i;
       d.rec_sync = sync_ + sofs;
-      d.nblk = (uint32_t)recover_blocks(plans[i]);
+      d.nblk = (uint32_t)recover_blocks(plans[i], false);
       const dmul_spectrum* si = spec_a(i);
       const dmul_spectrum* ti = spec_b(i);
       d.square = (si || ti) ? (si == ti ? 1 : 0) : ((a[i] == b[i] && na[i] == nb[i]) ? 1 : 0);

@@ -237,15 +237,19 @@ __global__ void k_fill32(uint32_t* __restrict__ out, size_t n, uint32_t v) {
 }
 
 constexpr int kRecPT = 5;
-constexpr int kRecBlock = kRecThreads * kRecPT;    // positions per workgroup
+// A lone product whose recovery would take fewer blocks than the device has
+// CUs runs it at 2 positions per thread instead (shorter per-thread chains,
+// 2.5 times the workgroups); 2 is the least the kernels take (a thread reads
+// the digits of the two positions before its first one from its neighbour).
+constexpr int kRecPTLean = 2;
+constexpr size_t kLeanRecBlocks = 256;
 
-size_t recover_blocks(const PlanDev& pl) {
-  return (size_t)((pl.n + pl.m + kRecBlock - 1) / kRecBlock);
+size_t recover_blocks(const PlanDev& pl, bool lean) {
+  const size_t blk = (size_t)kRecThreads * (lean ? kRecPTLean : kRecPT);    // positions per block
+  return (size_t)((pl.n + pl.m + blk - 1) / blk);
 }
 
-size_t recover_scratch_words(const PlanDev& pl) {
-  return (size_t)(pl.n + pl.m) + recover_blocks(pl) + 1;   // s, then carries (u32)
-}
+bool recover_lean(const PlanDev& pl) { return recover_blocks(pl, false) < kLeanRecBlocks; }
 
 // Workgroups of the grid-stride recovery passes: one round of what the
 // device holds at once (four 256-thread workgroups per CU: the recovery
@@ -286,10 +290,17 @@ hipError_t launch_recover(const Work& w, const Shape& sh, const Consts& cs, cons
   const RecTable rt = make_rec_table(cs, dt_host);
   const unsigned g = recover_grid(sh.max_nblk);
   const bool prefix = sh.max_nblk <= kPrefixBlocks;
-  hipLaunchKernelGGL(k_rec_crt<kRecPT>, dim3(g, 1, w.count), dim3(kRecThreads), 0, st, w, rt);
+  if (sh.rec_lean)
+    hipLaunchKernelGGL(k_rec_crt<kRecPTLean>, dim3(g, 1, w.count), dim3(kRecThreads), 0, st, w, rt);
+  else
+    hipLaunchKernelGGL(k_rec_crt<kRecPT>, dim3(g, 1, w.count), dim3(kRecThreads), 0, st, w, rt);
   if (!prefix) hipLaunchKernelGGL(k_rec_scan, dim3(1, 1, w.count), dim3(kScanThreads), 0, st, w, rt);
   if (marks) marks->mark(kRecCrt, st);
-  if (prefix)
+  if (sh.rec_lean && prefix)
+    hipLaunchKernelGGL((k_rec_apply<kRecPTLean, true>), dim3(g, 1, w.count), dim3(kRecThreads), 0, st, w, rt, dt);
+  else if (sh.rec_lean)
+    hipLaunchKernelGGL((k_rec_apply<kRecPTLean, false>), dim3(g, 1, w.count), dim3(kRecThreads), 0, st, w, rt, dt);
+  else if (prefix)
     hipLaunchKernelGGL((k_rec_apply<kRecPT, true>), dim3(g, 1, w.count), dim3(kRecThreads), 0, st, w, rt, dt);
   else
     hipLaunchKernelGGL((k_rec_apply<kRecPT, false>), dim3(g, 1, w.count), dim3(kRecThreads), 0, st, w, rt, dt);

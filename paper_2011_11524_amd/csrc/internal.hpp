@@ -151,6 +151,7 @@ struct Shape {
   int any_nonsquare;        // some product transforms two operands
   int row_iters;            // row groups per workgroup in the row pass
   uint32_t max_nblk;        // largest recovery grid among the products
+  int rec_lean;             // the recovery in short blocks (recover_blocks(pl, true))
 };
 
 // Launch wrappers (ntt.hip, carry.hip).  All enqueue on `stream` and return
@@ -186,8 +187,10 @@ hipError_t launch_small_queue(const Work& w, int tier, size_t lds, uint32_t* hea
 // Raises a kernel's dynamic-LDS limit to lds_bytes when above the default
 // 64 KB (once per kernel and size: the attribute call is host work).
 hipError_t allow_lds(const void* kernel, size_t lds_bytes);
-size_t recover_blocks(const PlanDev& pl);
-size_t recover_scratch_words(const PlanDev& pl);
+// Recovery blocks of a product: the default size, or (lean) the shorter
+// blocks of a lone product whose default recovery would not fill the CUs.
+size_t recover_blocks(const PlanDev& pl, bool lean);
+bool recover_lean(const PlanDev& pl);
 hipError_t launch_zero(uint64_t* out, size_t n, hipStream_t stream);
 // n 32-bit words of v (the scratch poisoning of contexts made with
 // DMUL_POISON set: workspaces start as garbage, never as the last product's).
