@@ -651,8 +651,9 @@ constexpr int col_loge(int logl) { return loge_for(logl); }
 // 4 points per thread, so the same transform runs on four times the
 // threads in a quarter of the per-thread chain, and narrower tiles (more
 // workgroups).  A 10^5-digit product (N = 3*2^12) runs 0.065 -> 0.045 ms
-// that way; in the batched workload, whose launches are large, it costs 2%,
-// so those keep 16 points per thread.
+// with the 4 points per thread, 0.034 ms with the narrower tiles as well;
+// in the batched workload, whose launches are large, 4 points per thread
+// cost 2%, so those keep 16.
 constexpr int kLeanMaxLog = 7;
 constexpr int lean_loge(int logl) { return logl < 2 ? logl : 2; }
 constexpr int kLeanMinGroups = 256;   // one workgroup per CU
@@ -685,12 +686,24 @@ constexpr int triples_for(int logl, int loge, int threads, int extra) {
 // 512 threads: there the forward tile takes 1024 threads and 8 columns,
 // whose register cap of 128 costs a small spill but took C3's forward
 // column pass from 198 to 173 us.
-constexpr int fwd_cols_per_tile(int logl, int loge) {
-  return cols_for(logl, loge, logl >= 11 ? 1024 : 512, 1 << logl);
+// Lean launches aim at a quarter of these thread targets: narrower tiles,
+// four times the workgroups (C1's column passes 8 -> 32 tiles per operand
+// or prime; 0.042 -> 0.034 ms).
+constexpr int lean_div(int logl, int loge) {
+  return logl <= kLeanMaxLog && loge == lean_loge(logl) && loge != col_loge(logl) ? 4 : 1;
 }
-constexpr int cols_per_tile(int logl, int loge) { return cols_for(logl, loge, 1024, (1 << logl) / 2); }
-constexpr int fwd_triples_per_tile(int logl, int loge) { return triples_for(logl, loge, 768, 1 << logl); }
-constexpr int triples_per_tile(int logl, int loge) { return triples_for(logl, loge, 1024, (1 << logl) / 2); }
+constexpr int fwd_cols_per_tile(int logl, int loge) {
+  return cols_for(logl, loge, (logl >= 11 ? 1024 : 512) / lean_div(logl, loge), 1 << logl);
+}
+constexpr int cols_per_tile(int logl, int loge) {
+  return cols_for(logl, loge, 1024 / lean_div(logl, loge), (1 << logl) / 2);
+}
+constexpr int fwd_triples_per_tile(int logl, int loge) {
+  return triples_for(logl, loge, 768 / lean_div(logl, loge), 1 << logl);
+}
+constexpr int triples_per_tile(int logl, int loge) {
+  return triples_for(logl, loge, 1024 / lean_div(logl, loge), (1 << logl) / 2);
+}
 constexpr uint64_t kRowMinGroups = 1024;
 // Points per thread (log2) and rows per workgroup in the row passes.
 constexpr int row_loge(int logl) { return loge_for(logl); }
@@ -784,8 +797,13 @@ static hipError_t rows_l(const Work& w, const Shape& sh, const Consts& cs, const
 // the long rows need about 170 registers (two wavefronts per SIMD): the
 // fused pass of C2's 1024-point rows took 60 us that way, 52 us this way.
 constexpr int fused_loge(int logl) { return logl <= 8 ? loge_for(logl) : 3; }
+// Threads of a fused row-pass workgroup: kRowThreads, a quarter of them in
+// a lean launch (four times the workgroups).
+constexpr int fused_threads(int logl, int loge) {
+  return logl <= kLeanMaxLog && loge == lean_loge(logl) && loge != fused_loge(logl) ? kRowThreads / 4 : kRowThreads;
+}
 constexpr int fused_rows_per_wg(int logl, int loge) {
-  return (kRowThreads >> (logl - loge)) < 1 ? 1 : (kRowThreads >> (logl - loge));
+  return (fused_threads(logl, loge) >> (logl - loge)) < 1 ? 1 : (fused_threads(logl, loge) >> (logl - loge));
 }
 
 // Workgroups of a fused row-pass launch: row groups over the tuned loop
