@@ -651,10 +651,11 @@ constexpr int col_loge(int logl) { return loge_for(logl); }
 // 4 points per thread, so the same transform runs on four times the
 // threads in a quarter of the per-thread chain, and narrower tiles (more
 // workgroups).  A 10^5-digit product (N = 3*2^12) runs 0.065 -> 0.045 ms
-// with the 4 points per thread, 0.034 ms with the narrower tiles as well;
-// in the batched workload, whose launches are large, 4 points per thread
-// cost 2%, so those keep 16.
-constexpr int kLeanMaxLog = 7;
+// with the 4 points per thread, 0.034 ms with the narrower tiles as well,
+// a 10^6-digit one (N = 3*2^16) 0.075 -> 0.041 ms; in the batched
+// workload, whose launches are large, 4 points per thread cost 2%, so
+// those keep 16.
+constexpr int kLeanMaxLog = 9;
 constexpr int lean_loge(int logl) { return logl < 2 ? logl : 2; }
 constexpr int kLeanMinGroups = 256;   // one workgroup per CU
 constexpr int col_stride(int logl, int loge) { return (1 << logl) + ((1 << logl) >> loge) + 1; }
