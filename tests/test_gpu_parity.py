@@ -671,3 +671,25 @@ def test_tuned_paths_and_streams(dm):
             c.tune_streams(17)
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("na,nb,count", [(5264, 5264, 300), (60000, 50000, 40)])
+def test_lean_and_default_launches_agree(dm, ctx, na, nb, count):
+    """A short product alone launches too few workgroups to fill the CUs,
+    so it takes the lean configuration (4 points per thread, narrow tiles,
+    512-position recovery blocks); the same length in a large batch takes
+    the default one (16 points per thread, wide tiles, 1280-position blocks).
+    Both give the same limbs, and a sample of them equals the oracle."""
+    pl = dm.plan(na, nb)
+    assert pl.N > 4096 and pl.log2_rows <= 9      # pass kernels, lean-eligible lengths
+    _note(f"lean vs default launches: {count} products of {na}x{nb} limbs (N = {pl.N})")
+    rng = np.random.default_rng(7000 + na)
+    host = [(rng.integers(0, 10 ** 19, size=na, dtype=np.uint64),
+             rng.integers(0, 10 ** 19, size=nb, dtype=np.uint64)) for _ in range(count)]
+    dev = [(dm.to_device(a), dm.to_device(b)) for a, b in host]
+    outs, st = ctx.batch(dev)
+    assert st == [0] * count
+    for (da, db), o in zip(dev, outs):
+        np.testing.assert_array_equal(dm.to_host(o), dm.to_host(ctx.mul(da, db)))
+    for i in (0, count - 1):
+        np.testing.assert_array_equal(dm.to_host(outs[i]), oracle.mul_ntt(*host[i]))
