@@ -338,11 +338,13 @@ int dmul_batch_ex(dmul_ctx* ctx, size_t count, const uint64_t* const* a, const s
  * DMUL_EINVAL (a length that is not a supported size class, or row_iters
  * outside 0..64). */
 int dmul_ctx_tune(dmul_ctx* ctx, uint64_t transform_len, int row_iters);
-/* Kernel path of products of transform length transform_len: 0 the
- * default rule (the whole-product kernel up to N = 4096 for launches of 8
- * or more products of that length, up to N = 2048 otherwise), 1 always the
- * whole-product kernel (N <= 4096 only), 2 always the pass kernels.  Table
- * lines "transform_len row_iters path" set it too.  Returns DMUL_OK or
+/* Kernel path of launches of 8 or more products of transform length
+ * transform_len (a batch class): 0 the default rule (the whole-product
+ * kernel up to N = 4096), 1 always the whole-product kernel (N <= 4096
+ * only), 2 always the pass kernels.  Fewer products of a length (a lone
+ * product, a small class) always take the default rule for them: the
+ * whole-product kernel up to N = 256, the pass kernels beyond.  Table lines
+ * "transform_len row_iters path" set it too.  Returns DMUL_OK or
  * DMUL_EINVAL. */
 int dmul_ctx_tune_path(dmul_ctx* ctx, uint64_t transform_len, int path);
 /* Number of side streams (1..16; 0 = the default 8) over which a batch's

@@ -421,7 +421,9 @@ int row_iters_for(const dmul_ctx* ctx, const PlanDev& pl) {
 }
 
 bool use_small(const dmul_ctx* ctx, const PlanDev& pl, size_t count) {
-  const int path = ctx->tune.path[pl.rad3 ? 1 : 0][pl.logN];
+  // a tuned path is a batch choice: launches of fewer products of the length
+  // take the default rule
+  const int path = count >= kSmallMinCount ? ctx->tune.path[pl.rad3 ? 1 : 0][pl.logN] : 0;
   if (path == 1) return pl.N <= kSmallMaxN;
   if (path == 2) return false;
   return small_fits(pl, count);

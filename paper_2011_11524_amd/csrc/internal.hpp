@@ -28,7 +28,11 @@ constexpr int kMaxLogC3 = 11;      // rows of 3 * 2^logC points: logC <= 11
 constexpr int kMaxLogR3 = 12;      // with C = 3M a column tile holds three columns of 2^logR points
 constexpr int kMinLogN3 = 4;       // lengths 3 * 2^e are used for e >= 4
 constexpr uint64_t kSmallMaxN = 4096;   // whole product in one workgroup up to this length
-constexpr uint64_t kSmallSoloMaxN = 2048;  // ... for a lone product (one workgroup vs the device)
+// ... for a lone product (or fewer than kSmallMinCount of one length): one
+// workgroup against the lean pass launches, which win from N = 384 (0.027
+// against 0.028 ms, and 0.031 against 0.083 ms at N = 3072; the kernel wins
+// at N = 192, 0.023 against 0.025 ms)
+constexpr uint64_t kSmallSoloMaxN = 256;
 constexpr size_t kSmallMinCount = 8;       // products of a class that make 4096 worth it
 constexpr int kMinK = 13;          // p1*p2 < 10^(3k): three base-10^k parts per coefficient
 // Allocation-free products (dmul_ex_noalloc) run in a static device array of

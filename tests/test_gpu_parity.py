@@ -200,7 +200,7 @@ def _sizes_at_most(dm, N, seed):
 
 def test_whole_product_kernel_every_class(dm, ctx):
     """Every transform length of the one-workgroup kernel (N <= 4096):
-    single products (that kernel up to N = 2048, the passes beyond), and
+    single products (that kernel up to N = 256, the passes beyond), and
     one batch with 8 products of every length (4 products, 4 squares), where
     every length takes the kernel; all against the oracle."""
     rng = np.random.default_rng(9100)
